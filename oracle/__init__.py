@@ -1,0 +1,208 @@
+"""CPU oracle for the ensemble Gillespie direct method in reduced precision.
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It is the plain,
+slow statement of what the GPU path computes (``ssa_oracle.c`` holds the
+arithmetic and cites the paper section of every step), and it shares no code
+with the GPU library.
+
+Models are passed as any object with the attributes ``n_species``,
+``n_reactions``, ``order`` and ``nu`` (M x N int arrays), ``law`` (M ints:
+0 mass action, 1 Hill repression, 2 Hill activation), ``rate`` (M floats:
+mass-action k_j or Hill v_j) and ``hill_reg``, ``hill_h``, ``hill_b``,
+``hill_K`` (M each). Precision modes are named by strings:
+``FP64``, ``FP32``, ``{MIX,UNI}_{F16,BF16}_{RTN,SR}`` and, for uniform mode,
+a ``_NORM`` suffix (running-max propensity normalisation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ssa_oracle.c")
+_LIB = os.path.join(_HERE, "libssa_oracle.so")
+
+STATUS_NAMES = ("DONE", "ABSORBED", "OVERFLOW", "CAPPED")
+FMT_FP64, FMT_FP32, FMT_FP16, FMT_BF16 = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with FMA contraction off (binary32/64 ops stay
+    single correctly rounded IEEE operations)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra", "-Wno-maybe-uninitialized", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32), ("n_reactions", ctypes.c_int32),
+                ("order", ctypes.c_void_p), ("nu", ctypes.c_void_p), ("law", ctypes.c_void_p),
+                ("rate", ctypes.c_void_p), ("hill_reg", ctypes.c_void_p), ("hill_h", ctypes.c_void_p),
+                ("hill_b", ctypes.c_void_p), ("hill_K", ctypes.c_void_p)]
+
+
+class _Mode(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int32), ("uniform", ctypes.c_int32), ("sr", ctypes.c_int32),
+                ("norm", ctypes.c_int32)]
+
+
+class _Run(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_void_p), ("t_end", ctypes.c_double), ("snap_t", ctypes.c_void_p),
+                ("n_snap", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("traj_id_base", ctypes.c_uint32), ("max_events", ctypes.c_uint64),
+                ("set_rate", ctypes.c_void_p), ("n_sets", ctypes.c_int64),
+                ("traj_per_set", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.or_simulate.restype = ctypes.c_int
+        lib.or_simulate.argtypes = [ctypes.POINTER(_Model), _Mode, ctypes.POINTER(_Run),
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        for name in ("or_philox_batch", "or_nlog64_batch", "or_nlog32_batch", "or_uniform_batch"):
+            getattr(lib, name).restype = None
+        lib.or_round16_batch.restype = None
+        lib.or_round16_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64]
+        _lib = lib
+    return _lib
+
+
+@dataclass(frozen=True)
+class Mode:
+    fmt: int
+    uniform: bool = False
+    sr: bool = False
+    norm: bool = False
+
+
+def parse_mode(name: str) -> Mode:
+    """Parse FP64 / FP32 / {MIX,UNI}_{F16,BF16}_{RTN,SR}[_NORM]."""
+    if name == "FP64":
+        return Mode(FMT_FP64)
+    if name == "FP32":
+        return Mode(FMT_FP32)
+    parts = name.split("_")
+    if len(parts) not in (3, 4) or parts[0] not in ("MIX", "UNI") or parts[1] not in ("F16", "BF16") \
+            or parts[2] not in ("RTN", "SR") or (len(parts) == 4 and (parts[3] != "NORM" or parts[0] != "UNI")):
+        raise ValueError(f"unknown precision mode {name!r}")
+    return Mode(FMT_FP16 if parts[1] == "F16" else FMT_BF16, parts[0] == "UNI", parts[2] == "SR",
+                len(parts) == 4)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: int | None = None,
+             indices=None, traj_id_base: int = 0, max_events: int = 0, set_rate=None,
+             traj_per_set: int = 0, threads: int = 1):
+    """Run trajectories ``indices`` (default ``range(n_traj)``) of an ensemble.
+
+    Returns a dict with ``snap`` [K, N, count] int32, ``n_events`` uint64,
+    ``t_last`` float64 and ``status`` uint8 per trajectory.
+    """
+    lib = _load()
+    if indices is None:
+        indices = np.arange(int(n_traj), dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.int64)
+    N, M = int(model.n_species), int(model.n_reactions)
+    keep = []
+
+    def arr(a, dt):
+        b = np.ascontiguousarray(a, dtype=dt)
+        keep.append(b)
+        return b
+
+    order = arr(model.order, np.int32).reshape(M, N)
+    nu = arr(model.nu, np.int32).reshape(M, N)
+    law = arr(model.law, np.int32)
+    rate = arr(model.rate, np.float64)
+    hr, hh = arr(model.hill_reg, np.int32), arr(model.hill_h, np.int32)
+    hb, hK = arr(model.hill_b, np.float64), arr(model.hill_K, np.float64)
+    md = _Model(N, M, _ptr(order), _ptr(nu), _ptr(law), _ptr(rate), _ptr(hr), _ptr(hh), _ptr(hb), _ptr(hK))
+    m = parse_mode(mode)
+    cm = _Mode(m.fmt, int(m.uniform), int(m.sr), int(m.norm))
+    x0a = arr(x0, np.int32)
+    ts = arr(snap_t, np.float64)
+    sr_tab = None if set_rate is None else arr(set_rate, np.float64)
+    n_sets = 0 if sr_tab is None else sr_tab.size // M
+    run = _Run(_ptr(x0a), float(t_end), _ptr(ts), ts.size, int(seed) & (2**64 - 1),
+               int(traj_id_base), int(max_events), _ptr(sr_tab), n_sets, int(traj_per_set))
+    count = idx.size
+    K = ts.size
+    snap = np.zeros((K, N, count), dtype=np.int32)
+    n_ev = np.zeros(count, dtype=np.uint64)
+    t_last = np.zeros(count, dtype=np.float64)
+    status = np.zeros(count, dtype=np.uint8)
+    rc = lib.or_simulate(ctypes.byref(md), cm, ctypes.byref(run), _ptr(idx), count, _ptr(snap),
+                         _ptr(n_ev), _ptr(t_last), _ptr(status), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return {"snap": snap, "n_events": n_ev, "t_last": t_last, "status": status}
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of counters ctr [n,4] under keys key [n,2] -> [n,4] uint32."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.empty_like(c)
+    lib.or_philox_batch(ctypes.c_void_p(c.ctypes.data), ctypes.c_void_p(k.ctypes.data),
+                        ctypes.c_void_p(out.ctypes.data), ctypes.c_int64(c.shape[0]))
+    return out
+
+
+def nlog64(u):
+    """-ln(u), FP64 project logarithm, for u in (0, 1]."""
+    lib = _load()
+    a = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(a)
+    lib.or_nlog64_batch(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(out.ctypes.data), ctypes.c_int64(a.size))
+    return out
+
+
+def nlog32(u):
+    """-ln(u), FP32 project logarithm, for u in (0, 1]."""
+    lib = _load()
+    a = np.ascontiguousarray(u, dtype=np.float32)
+    out = np.empty_like(a)
+    lib.or_nlog32_batch(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(out.ctypes.data), ctypes.c_int64(a.size))
+    return out
+
+
+def round16(fmt: int, v, rb=None):
+    """Round doubles to fp16 (fmt=2) or bf16 (fmt=3): RNE, or SR with halfwords rb."""
+    lib = _load()
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    r = None if rb is None else np.ascontiguousarray(np.broadcast_to(rb, a.shape), dtype=np.int32)
+    out = np.empty_like(a)
+    lib.or_round16_batch(int(fmt), a.ctypes.data, None if r is None else r.ctypes.data,
+                         out.ctypes.data, a.size)
+    return out
+
+
+def uniforms(w):
+    """(u53 from word pairs, u24 from the first word of each pair) for w [n,2]."""
+    lib = _load()
+    a = np.ascontiguousarray(w, dtype=np.uint32).reshape(-1, 2)
+    u53 = np.empty(a.shape[0], dtype=np.float64)
+    u24 = np.empty(a.shape[0], dtype=np.float32)
+    lib.or_uniform_batch(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(u53.ctypes.data),
+                         ctypes.c_void_p(u24.ctypes.data), ctypes.c_int64(a.shape[0]))
+    return u53, u24
