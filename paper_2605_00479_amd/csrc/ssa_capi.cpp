@@ -1,0 +1,1025 @@
+// ssa_capi.cpp - host side of libssa_rp.so: the C ABI declared in ssa_rp.h.
+//
+//  * ssa_model_create validates a reaction network and keeps a copy.
+//  * ssa_ensemble_run rounds the rate constants once to the run's precision,
+//    generates the network description for the device template
+//    (ssa_device.hip), compiles it with hipRTC for gfx950 (cached in memory
+//    and on disk), uploads tables and launches the persistent kernel, in one
+//    launch or in snapshot-window chunks replayed from a captured hipGraph.
+//  * getters copy results out; ssa_run_info_get reports HIP-event timings.
+#include "ssa_rp.h"
+
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <dlfcn.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "ssa_device_src.inc"  // const char kDeviceSource[] (ssa_device.hip)
+
+namespace {
+
+// ------------------------------------------------------------------ errors
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(SSA_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+// ------------------------------------------------------------------ models
+struct Model {
+    int N = 0, M = 0;
+    std::vector<int32_t> order;  // [M][N]
+    std::vector<int32_t> nu;     // [M][N]
+    std::vector<ssa_law> law;    // [M]
+};
+
+constexpr int kMaxSpecies = 32;
+constexpr int kMaxReactions = 64;
+constexpr int kMaxOrder = 4;
+constexpr int kMaxSnap = 65536;
+
+int64_t factorial(int n)
+{
+    int64_t f = 1;
+    for (int i = 2; i <= n; ++i)
+        f *= i;
+    return f;
+}
+
+// Propensity constant of reaction j from its k: mass action divides by
+// prod_s o_s! (one binary64 division), Hill uses vmax as given.
+double primary_constant(const Model &md, int j, double k)
+{
+    if (md.law[j].kind != SSA_LAW_MASS_ACTION)
+        return k;
+    int64_t d = 1;
+    for (int s = 0; s < md.N; ++s)
+        d *= factorial(md.order[(size_t)j * md.N + s]);
+    return k / (double)d;
+}
+
+// Round-to-nearest-even of a binary64 value onto a floating grid with p
+// significand bits, smallest normal exponent emin and overflow threshold ovf.
+double round_to_grid(double v, int p, int emin, double ovf)
+{
+    if (std::isnan(v) || std::isinf(v) || v == 0.0)
+        return v;
+    double a = std::fabs(v);
+    int e = std::ilogb(a);
+    if (e < emin)
+        e = emin;
+    double step = std::ldexp(1.0, e - (p - 1));
+    double r = std::nearbyint(a / step) * step;  // default rounding: ties to even
+    if (r >= ovf)
+        r = INFINITY;
+    return std::copysign(r, v);
+}
+
+// Value of constant v in the run's propensity type, widened to double.
+double to_prop_type(int fmt, double v)
+{
+    switch (fmt) {
+    case SSA_FMT_FP64: return v;
+    case SSA_FMT_FP32: return (double)(float)v;
+    case SSA_FMT_FP16: return round_to_grid(v, 11, -14, 65536.0);
+    default: return round_to_grid(v, 8, -126, std::ldexp(1.0, 128));
+    }
+}
+
+}  // namespace
+
+struct ssa_model {
+    Model m;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ codegen
+int mass_action_total_order(const Model &md, int j)
+{
+    int t = 0;
+    for (int s = 0; s < md.N; ++s)
+        t += md.order[(size_t)j * md.N + s];
+    return t;
+}
+
+int reaction_slots(const Model &md, int j)
+{
+    const ssa_law &L = md.law[j];
+    if (L.kind == SSA_LAW_MASS_ACTION)
+        return 2 * mass_action_total_order(md, j);
+    return L.h + (L.kind == SSA_LAW_HILL_REPRESS ? 4 : 5);
+}
+
+// Device description of one network: propensity op sequence with its static
+// rounding slots, and the integer update x += nu_mu.
+std::string gen_model(const Model &md, int idx)
+{
+    int nprop = 0;
+    for (int j = 0; j < md.M; ++j)
+        nprop += reaction_slots(md, j);
+    std::ostringstream o;
+    o << "struct Md" << idx << " {\n"
+      << "  static constexpr int N = " << md.N << ", M = " << md.M << ", NPROP = " << nprop << ";\n"
+      << "  template <class P, class PoolT>\n"
+      << "  __device__ static __forceinline__ void propensities(const i32 (&x)[N], const typename P::T (&c)[M],"
+      << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool) {\n"
+      << "    typedef typename P::T T;\n"
+      << "    (void)hill; (void)pool;\n";
+    int slot = 0;
+    for (int j = 0; j < md.M; ++j) {
+        const ssa_law &L = md.law[j];
+        if (L.kind == SSA_LAW_MASS_ACTION) {
+            if (mass_action_total_order(md, j) == 0) {
+                o << "    a[" << j << "] = c[" << j << "];\n";
+                continue;
+            }
+            o << "    { T acc = c[" << j << "];\n";
+            std::string zero;
+            for (int s = 0; s < md.N; ++s) {
+                int os = md.order[(size_t)j * md.N + s];
+                for (int i = 0; i < os; ++i) {
+                    o << "      acc = P::mul(acc, P::cvt(x[" << s << "] - " << i << ", pool.hw(" << slot
+                      << ")), pool.hw(" << slot + 1 << "));\n";
+                    slot += 2;
+                }
+                if (os > 0) {
+                    if (!zero.empty())
+                        zero += " || ";
+                    zero += "x[" + std::to_string(s) + "] < " + std::to_string(os);
+                }
+            }
+            o << "      a[" << j << "] = (" << zero << ") ? (T)0 : acc; }\n";
+        } else {
+            int b = slot;
+            o << "    { T xr = P::cvt(x[" << L.regulator << "], pool.hw(" << b << "));\n"
+              << "      T q = P::div(xr, hill[" << 2 * j + 1 << "], pool.hw(" << b + 1 << "));\n"
+              << "      T qh = q;\n";
+            int sl = b + 2;
+            for (int i = 1; i < L.h; ++i)
+                o << "      qh = P::mul(qh, q, pool.hw(" << sl++ << "));\n";
+            o << "      T d = P::add((T)1, qh, pool.hw(" << sl++ << "));\n";
+            if (L.kind == SSA_LAW_HILL_REPRESS) {
+                o << "      T f = P::div(c[" << j << "], d, pool.hw(" << sl++ << "));\n";
+            } else {
+                o << "      T g = P::mul(c[" << j << "], qh, pool.hw(" << sl++ << "));\n"
+                  << "      T f = P::div(g, d, pool.hw(" << sl++ << "));\n";
+            }
+            o << "      a[" << j << "] = P::add(hill[" << 2 * j << "], f, pool.hw(" << sl++ << ")); }\n";
+            slot = sl;
+        }
+    }
+    o << "  }\n"
+      << "  __device__ static __forceinline__ void update(i32 (&x)[N], int mu) {\n";
+    for (int s = 0; s < md.N; ++s) {
+        std::string terms;
+        for (int j = 0; j < md.M; ++j) {
+            int d = md.nu[(size_t)j * md.N + s];
+            if (d == 0)
+                continue;
+            if (!terms.empty())
+                terms += " + ";
+            terms += "(mu == " + std::to_string(j) + " ? " + std::to_string(d) + " : 0)";
+        }
+        if (!terms.empty())
+            o << "    x[" << s << "] += " << terms << ";\n";
+    }
+    o << "  }\n};\n";
+    return o.str();
+}
+
+struct ModeSpec {
+    int fmt, accum, rnd, norm;
+    std::string policy() const
+    {
+        if (fmt == SSA_FMT_FP64)
+            return "PrecF64";
+        if (fmt == SSA_FMT_FP32)
+            return "PrecF32";
+        std::string f = fmt == SSA_FMT_FP16 ? "FMT_FP16" : "FMT_BF16";
+        return "Prec16<" + f + ", " + (rnd == SSA_RND_SR ? "true" : "false") + ", " +
+               (accum == SSA_ACC_UNIFORM ? "true" : "false") + ", " +
+               (norm == SSA_NORM_RUNNING_MAX ? "true" : "false") + ">";
+    }
+};
+
+std::string gen_source(const std::vector<const Model *> &models, const ModeSpec &ms,
+                       const std::vector<bool> &per_lane_rates)
+{
+    std::ostringstream o;
+    o << "#define SSA_N_ITEMS " << models.size() << "\n" << kDeviceSource << "\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << gen_model(*models[i], (int)i);
+    o << "typedef " << ms.policy() << " PrecRun;\n"
+      << "extern \"C\" __global__ void __launch_bounds__(256) ssa_kernel(LaunchArgs L) {\n"
+      << "  const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n"
+      << "  u32 it = wave % SSA_N_ITEMS;\n"
+      << "  for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
+      << "    switch (it) {\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << "    case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
+          << ">(L, L.item[" << i << "]); break;\n";
+    o << "    default: break;\n"
+      << "    }\n"
+      << "    it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "  }\n"
+      << "}\n"
+      << "extern \"C\" __global__ void ssa_fill_u32(u32 *p, u32 n, u32 v) {\n"
+      << "  u32 i = blockIdx.x * blockDim.x + threadIdx.x;\n"
+      << "  if (i < n) p[i] = v;\n"
+      << "}\n";
+    return o.str();
+}
+
+// ------------------------------------------------------------------ JIT
+const char *const kJitOptions[] = {"-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
+                                   "-Xclang", "-packed-fp32-ops"};
+
+uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull)
+{
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string cache_dir()
+{
+    if (const char *e = std::getenv("SSA_RP_CACHE_DIR"))
+        return e;
+    Dl_info info;
+    if (dladdr((void *)&cache_dir, &info) && info.dli_fname) {
+        std::string p = info.dli_fname;
+        size_t sl = p.find_last_of('/');
+        if (sl != std::string::npos)
+            return p.substr(0, sl) + "/_kcache";
+    }
+    return "_kcache";
+}
+
+struct CompiledKernel {
+    std::vector<char> code;
+};
+
+int compile_source(const std::string &src, const std::string &arch, std::vector<char> &code)
+{
+    const std::string key = arch + "\n" + src;
+    uint64_t h = fnv1a(key);
+    for (const char *opt : kJitOptions)
+        h = fnv1a(opt, h);
+    char name[64];
+    std::snprintf(name, sizeof name, "%016llx.co", (unsigned long long)h);
+    const std::string dir = cache_dir();
+    const std::string path = dir + "/" + name;
+    {
+        std::ifstream in(path, std::ios::binary);
+        if (in) {
+            code.assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
+            if (!code.empty())
+                return SSA_OK;
+        }
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "ssa_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(SSA_E_COMPILE, "hiprtcCreateProgram failed");
+    std::vector<const char *> opts;
+    std::string archopt = "--offload-arch=" + arch;
+    opts.push_back(archopt.c_str());
+    for (const char *opt : kJitOptions)
+        opts.push_back(opt);
+    hiprtcResult rc = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls)
+            hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(SSA_E_COMPILE, "hipRTC compilation failed: " + log.substr(0, 4000));
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    code.resize(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    // best-effort disk cache (write to a temporary name, then rename)
+    ::mkdir(dir.c_str(), 0755);
+    std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    {
+        std::ofstream out(tmp, std::ios::binary);
+        if (out)
+            out.write(code.data(), (std::streamsize)code.size());
+    }
+    std::rename(tmp.c_str(), path.c_str());
+    return SSA_OK;
+}
+
+struct Loaded {
+    hipModule_t mod = nullptr;
+    hipFunction_t kernel = nullptr;
+    hipFunction_t fill = nullptr;
+    int vgprs = -1;
+};
+
+std::mutex g_jit_mu;
+std::unordered_map<std::string, Loaded> g_loaded;  // key: device + source hash
+
+int get_kernel(const std::string &src, Loaded &out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const std::string key = std::to_string(dev) + ":" + std::to_string(fnv1a(src)) + ":" +
+                            std::to_string(src.size());
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    auto it = g_loaded.find(key);
+    if (it != g_loaded.end()) {
+        out = it->second;
+        return SSA_OK;
+    }
+    std::vector<char> code;
+    int rc = compile_source(src, "gfx950", code);
+    if (rc != SSA_OK)
+        return rc;
+    Loaded ld;
+    HIP_TRY(hipModuleLoadData(&ld.mod, code.data()));
+    HIP_TRY(hipModuleGetFunction(&ld.kernel, ld.mod, "ssa_kernel"));
+    HIP_TRY(hipModuleGetFunction(&ld.fill, ld.mod, "ssa_fill_u32"));
+    int regs = -1;
+    if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, ld.kernel) == hipSuccess)
+        ld.vgprs = regs;
+    g_loaded[key] = ld;
+    out = ld;
+    return SSA_OK;
+}
+
+// ------------------------------------------------------------------ launch arguments
+// Must match LaunchArgs / ItemArgs in ssa_device.hip (same field order and types).
+struct ItemArgsH {
+    const void *rates;
+    const void *hill;
+    const int32_t *x0;
+    int32_t *snap;
+    uint64_t *n_events;
+    double *t_last;
+    unsigned char *status;
+    int32_t *cx;
+    double *ct;
+    uint64_t *cn;
+    int32_t *ck;
+    float *cm;
+    uint32_t *counter;
+    uint32_t E;
+    uint32_t traj_per_set;
+    uint32_t id_base;
+    uint32_t pad;
+};
+
+constexpr int kMaxItems = 8;
+
+struct LaunchArgsHead {
+    const double *snap_t64;
+    const float *snap_t32;
+    double t_end64;
+    float t_end32;
+    int32_t K;
+    int32_t k_lo, k_hi;
+    int32_t first, last;
+    uint32_t seed_lo, seed_hi;
+    uint64_t max_events;
+};
+
+template <int NI>
+struct LaunchArgsH {
+    LaunchArgsHead h;
+    ItemArgsH item[NI];
+};
+
+// ------------------------------------------------------------------ validation
+int validate_mode(const ssa_run_desc *d)
+{
+    if (d->format < SSA_FMT_FP64 || d->format > SSA_FMT_BF16)
+        return fail(SSA_E_INVALID, "format must be one of SSA_FMT_*");
+    if (d->accum != SSA_ACC_MIXED && d->accum != SSA_ACC_UNIFORM)
+        return fail(SSA_E_INVALID, "accum must be SSA_ACC_MIXED or SSA_ACC_UNIFORM");
+    if (d->rounding != SSA_RND_RTN && d->rounding != SSA_RND_SR)
+        return fail(SSA_E_INVALID, "rounding must be SSA_RND_RTN or SSA_RND_SR");
+    if (d->norm != SSA_NORM_NONE && d->norm != SSA_NORM_RUNNING_MAX)
+        return fail(SSA_E_INVALID, "norm must be SSA_NORM_NONE or SSA_NORM_RUNNING_MAX");
+    if (d->format <= SSA_FMT_FP32 &&
+        (d->accum != SSA_ACC_MIXED || d->rounding != SSA_RND_RTN || d->norm != SSA_NORM_NONE))
+        return fail(SSA_E_INVALID, "FP64/FP32 take accum=MIXED, rounding=RTN, norm=NONE");
+    if (d->norm == SSA_NORM_RUNNING_MAX && d->accum != SSA_ACC_UNIFORM)
+        return fail(SSA_E_UNSUPPORTED, "propensity normalisation is defined for uniform 16-bit mode only");
+    return SSA_OK;
+}
+
+int validate_desc(const ssa_run_desc *d)
+{
+    if (!d)
+        return fail(SSA_E_INVALID, "desc is NULL");
+    if (!d->items || d->n_items < 1 || d->n_items > kMaxItems)
+        return fail(SSA_E_INVALID, "n_items must be in [1, 8] with a non-NULL items array");
+    if (!(d->t_end > 0.0) || !std::isfinite(d->t_end))
+        return fail(SSA_E_INVALID, "t_end must be finite and > 0");
+    if (d->n_snap < 0 || d->n_snap > kMaxSnap)
+        return fail(SSA_E_INVALID, "n_snap must be in [0, 65536]");
+    if (d->n_snap > 0 && !d->snap_t)
+        return fail(SSA_E_INVALID, "snap_t is NULL");
+    for (int k = 0; k < d->n_snap; ++k) {
+        double tk = d->snap_t[k];
+        if (!(tk >= 0.0) || !(tk <= d->t_end))
+            return fail(SSA_E_INVALID, "snapshot times must lie in [0, t_end]");
+        if (k > 0 && !(tk >= d->snap_t[k - 1]))
+            return fail(SSA_E_INVALID, "snapshot times must be ascending");
+    }
+    int rc = validate_mode(d);
+    if (rc != SSA_OK)
+        return rc;
+    if (d->n_chunks < 0 || d->n_chunks > 4096)
+        return fail(SSA_E_INVALID, "n_chunks must be in [0, 4096]");
+    if (d->block_size != 0 && (d->block_size < 64 || d->block_size > 256 || d->block_size % 64 != 0))
+        return fail(SSA_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
+    if (d->grid_size < 0)
+        return fail(SSA_E_INVALID, "grid_size must be >= 0");
+    uint64_t total = 0;
+    for (int i = 0; i < d->n_items; ++i) {
+        const ssa_item &it = d->items[i];
+        if (!it.model)
+            return fail(SSA_E_INVALID, "item model is NULL");
+        if (!it.x0)
+            return fail(SSA_E_INVALID, "item x0 is NULL");
+        if (it.n_traj < 0 || it.n_traj >= (int64_t)1 << 31)
+            return fail(SSA_E_INVALID, "n_traj must be in [0, 2^31)");
+        for (int s = 0; s < it.model->m.N; ++s)
+            if (it.x0[s] < 0)
+                return fail(SSA_E_INVALID, "initial counts must be >= 0");
+        if (it.set_rates) {
+            if (it.n_sets < 1 || it.traj_per_set < 1 || it.traj_per_set >= ((int64_t)1 << 31) ||
+                it.n_traj > it.n_sets * it.traj_per_set)
+                return fail(SSA_E_INVALID, "set_rates needs n_sets >= 1, traj_per_set >= 1 and "
+                                           "n_traj <= n_sets * traj_per_set");
+            const int M = it.model->m.M;
+            for (int64_t r = 0; r < it.n_sets * M; ++r)
+                if (!(it.set_rates[r] >= 0.0) || !std::isfinite(it.set_rates[r]))
+                    return fail(SSA_E_INVALID, "set_rates must be finite and >= 0");
+        }
+        total += (uint64_t)it.n_traj;
+    }
+    if ((uint64_t)d->traj_id_base + total > 0xFFFFFFFFull)
+        return fail(SSA_E_INVALID, "traj_id_base + total trajectories must be < 2^32");
+    return SSA_OK;
+}
+
+// Kernel source and flags for a descriptor (no device needed).
+int build_source(const ssa_run_desc *d, std::string &src)
+{
+    std::vector<const Model *> models;
+    std::vector<bool> per_lane;
+    for (int i = 0; i < d->n_items; ++i) {
+        models.push_back(&d->items[i].model->m);
+        per_lane.push_back(d->items[i].set_rates != nullptr && d->items[i].n_sets > 1);
+    }
+    ModeSpec ms{d->format, d->accum, d->rounding, d->norm};
+    src = gen_source(models, ms, per_lane);
+    return SSA_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ run object
+struct ItemBuf {
+    int N = 0, M = 0;
+    int64_t E = 0;
+    int32_t *snap = nullptr;
+    uint64_t *nev = nullptr;
+    double *tlast = nullptr;
+    uint8_t *status = nullptr;
+    int32_t *cx = nullptr;
+    double *ct = nullptr;
+    uint64_t *cn = nullptr;
+    int32_t *ck = nullptr;
+    float *cm = nullptr;
+    void *rates = nullptr;
+    void *hill = nullptr;
+    int32_t *x0 = nullptr;
+    uint32_t traj_per_set = 0;
+    uint32_t id_base = 0;
+};
+
+struct ssa_run {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int K = 0;
+    int n_launch = 0;
+    int block = 0, grid = 0, vgprs = -1;
+    bool graph = false;
+    std::vector<ItemBuf> items;
+    std::vector<void *> owned;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> kev;  // start/stop per launch (non-graph runs)
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gx = nullptr;
+    hipStream_t cap = nullptr;
+    double *t64 = nullptr;
+    float *t32 = nullptr;
+    uint32_t *counters = nullptr;
+};
+
+namespace {
+
+template <class T>
+int dalloc(ssa_run *r, T **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0)
+        return SSA_OK;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    r->owned.push_back(q);
+    *p = (T *)q;
+    return SSA_OK;
+}
+
+template <int NI>
+int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks)
+{
+    LaunchArgsH<NI> A;
+    std::memset(&A, 0, sizeof A);
+    A.h.snap_t64 = r->t64;
+    A.h.snap_t32 = r->t32;
+    A.h.t_end64 = d->t_end;
+    A.h.t_end32 = (float)d->t_end;
+    A.h.K = r->K;
+    A.h.seed_lo = (uint32_t)d->seed;
+    A.h.seed_hi = (uint32_t)(d->seed >> 32);
+    A.h.max_events = d->max_events;
+    const int nI = d->n_items;
+    hipStream_t s = r->graph ? r->cap : r->stream;
+    // one zeroed counter per (chunk, item)
+    {
+        uint32_t n = (uint32_t)(n_chunks * nI);
+        uint32_t v = 0;
+        void *args[] = {&r->counters, &n, &v};
+        HIP_TRY(hipModuleLaunchKernel(ld.fill, (n + 255) / 256, 1, 1, 256, 1, 1, 0, s, args, nullptr));
+    }
+    for (int c = 0; c < n_chunks; ++c) {
+        const int k_lo = (int)((int64_t)c * r->K / n_chunks);
+        const int k_hi = c == n_chunks - 1 ? r->K : (int)((int64_t)(c + 1) * r->K / n_chunks);
+        A.h.k_lo = k_lo;
+        A.h.k_hi = k_hi;
+        A.h.first = c == 0;
+        A.h.last = c == n_chunks - 1;
+        for (int i = 0; i < nI; ++i) {
+            const ItemBuf &b = r->items[i];
+            ItemArgsH &ia = A.item[i];
+            ia.rates = b.rates;
+            ia.hill = b.hill;
+            ia.x0 = b.x0;
+            ia.snap = b.snap ? b.snap + (size_t)k_lo * b.N * b.E : nullptr;
+            ia.n_events = b.nev;
+            ia.t_last = b.tlast;
+            ia.status = b.status;
+            ia.cx = b.cx;
+            ia.ct = b.ct;
+            ia.cn = b.cn;
+            ia.ck = b.ck;
+            ia.cm = b.cm;
+            ia.counter = r->counters + (size_t)c * nI + i;
+            ia.E = (uint32_t)b.E;
+            ia.traj_per_set = b.traj_per_set;
+            ia.id_base = b.id_base;
+        }
+        void *args[] = {&A};
+        if (!r->graph)
+            HIP_TRY(hipEventRecord(r->kev[2 * c], s));
+        HIP_TRY(hipModuleLaunchKernel(ld.kernel, r->grid, 1, 1, r->block, 1, 1, 0, s, args, nullptr));
+        if (!r->graph)
+            HIP_TRY(hipEventRecord(r->kev[2 * c + 1], s));
+    }
+    return SSA_OK;
+}
+
+int dispatch_launch(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks)
+{
+    switch (d->n_items) {
+    case 1: return launch_all<1>(r, d, ld, n_chunks);
+    case 2: return launch_all<2>(r, d, ld, n_chunks);
+    case 3: return launch_all<3>(r, d, ld, n_chunks);
+    case 4: return launch_all<4>(r, d, ld, n_chunks);
+    case 5: return launch_all<5>(r, d, ld, n_chunks);
+    case 6: return launch_all<6>(r, d, ld, n_chunks);
+    case 7: return launch_all<7>(r, d, ld, n_chunks);
+    default: return launch_all<8>(r, d, ld, n_chunks);
+    }
+}
+
+int run_impl(const ssa_run_desc *d, ssa_run *r)
+{
+    HIP_TRY(hipGetDevice(&r->device));
+    r->stream = (hipStream_t)d->hip_stream;
+    r->K = d->n_snap;
+    std::string src;
+    build_source(d, src);
+    Loaded ld;
+    int rc = get_kernel(src, ld);
+    if (rc != SSA_OK)
+        return rc;
+    r->vgprs = ld.vgprs;
+
+    const bool wide = d->format == SSA_FMT_FP64;
+    int n_chunks = d->n_chunks <= 1 ? 1 : d->n_chunks;
+    if (n_chunks > std::max(r->K, 1))
+        n_chunks = std::max(r->K, 1);
+
+    // snapshot times in both clock types
+    std::vector<float> t32(r->K);
+    for (int k = 0; k < r->K; ++k)
+        t32[k] = (float)d->snap_t[k];
+    if ((rc = dalloc(r, &r->t64, (size_t)r->K)) || (rc = dalloc(r, &r->t32, (size_t)r->K)))
+        return rc;
+    if (r->K) {
+        HIP_TRY(hipMemcpy(r->t64, d->snap_t, sizeof(double) * r->K, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(r->t32, t32.data(), sizeof(float) * r->K, hipMemcpyHostToDevice));
+    }
+    if ((rc = dalloc(r, &r->counters, (size_t)n_chunks * d->n_items)))
+        return rc;
+
+    uint64_t id_base = d->traj_id_base;
+    int64_t total = 0;
+    std::vector<std::vector<char>> staging;  // host copies of the tables (uploaded synchronously)
+    for (int i = 0; i < d->n_items; ++i) {
+        const ssa_item &it = d->items[i];
+        const Model &md = it.model->m;
+        ItemBuf b;
+        b.N = md.N;
+        b.M = md.M;
+        b.E = it.n_traj;
+        b.id_base = (uint32_t)id_base;
+        id_base += (uint64_t)it.n_traj;
+        total += it.n_traj;
+        const bool per_lane = it.set_rates != nullptr && it.n_sets > 1;
+        b.traj_per_set = per_lane ? (uint32_t)it.traj_per_set : 0u;
+        // rate table in the propensity type
+        const int64_t n_sets = it.set_rates ? (per_lane ? it.n_sets : 1) : 1;
+        const size_t tsz = wide ? sizeof(double) : sizeof(float);
+        staging.emplace_back((size_t)n_sets * md.M * tsz);
+        char *rt = staging.back().data();
+        for (int64_t sidx = 0; sidx < n_sets; ++sidx)
+            for (int j = 0; j < md.M; ++j) {
+                double k = it.set_rates ? it.set_rates[sidx * md.M + j] : md.law[j].k;
+                double v = to_prop_type(d->format, primary_constant(md, j, k));
+                if (wide)
+                    ((double *)rt)[sidx * md.M + j] = v;
+                else
+                    ((float *)rt)[sidx * md.M + j] = (float)v;
+            }
+        staging.emplace_back((size_t)2 * md.M * tsz);
+        char *ht = staging.back().data();
+        for (int j = 0; j < md.M; ++j) {
+            bool hill = md.law[j].kind != SSA_LAW_MASS_ACTION;
+            double bv = to_prop_type(d->format, hill ? md.law[j].basal : 0.0);
+            double kv = to_prop_type(d->format, hill ? md.law[j].K : 1.0);
+            if (wide) {
+                ((double *)ht)[2 * j] = bv;
+                ((double *)ht)[2 * j + 1] = kv;
+            } else {
+                ((float *)ht)[2 * j] = (float)bv;
+                ((float *)ht)[2 * j + 1] = (float)kv;
+            }
+        }
+        char *rates_d = nullptr, *hill_d = nullptr;
+        if ((rc = dalloc(r, &rates_d, staging[staging.size() - 2].size())) ||
+            (rc = dalloc(r, &hill_d, staging.back().size())) || (rc = dalloc(r, &b.x0, (size_t)md.N)))
+            return rc;
+        HIP_TRY(hipMemcpy(rates_d, rt, staging[staging.size() - 2].size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(hill_d, ht, staging.back().size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b.x0, it.x0, sizeof(int32_t) * md.N, hipMemcpyHostToDevice));
+        b.rates = rates_d;
+        b.hill = hill_d;
+        // outputs
+        const size_t E = (size_t)it.n_traj;
+        b.snap = it.d_snap;
+        if (!b.snap && (rc = dalloc(r, &b.snap, (size_t)r->K * md.N * E)))
+            return rc;
+        b.nev = it.d_n_events;
+        if (!b.nev && (rc = dalloc(r, &b.nev, E)))
+            return rc;
+        b.tlast = it.d_t_last;
+        if (!b.tlast && (rc = dalloc(r, &b.tlast, E)))
+            return rc;
+        b.status = it.d_status;
+        if (!b.status && (rc = dalloc(r, &b.status, E)))
+            return rc;
+        if (n_chunks > 1) {
+            if ((rc = dalloc(r, &b.cx, (size_t)md.N * E)) || (rc = dalloc(r, &b.ct, E)) ||
+                (rc = dalloc(r, &b.cn, E)) || (rc = dalloc(r, &b.ck, E)) || (rc = dalloc(r, &b.cm, E)))
+                return rc;
+        }
+        r->items.push_back(b);
+    }
+
+    // launch shape: enough waves to cover the ensemble, at most what stays resident
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
+    r->block = d->block_size ? d->block_size : 256;
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel, r->block, 0));
+    if (per_cu < 1)
+        per_cu = 1;
+    int64_t need = (total + r->block - 1) / r->block;
+    int64_t resident = (int64_t)per_cu * cus;
+    int64_t grid = d->grid_size ? d->grid_size : std::max<int64_t>(1, std::min(need, resident));
+    r->grid = (int)grid;
+
+    HIP_TRY(hipEventCreate(&r->ev0));
+    HIP_TRY(hipEventCreate(&r->ev1));
+    r->n_launch = n_chunks;
+    r->graph = n_chunks > 1;
+    if (!r->graph) {
+        r->kev.resize(2 * n_chunks);
+        for (auto &e : r->kev)
+            HIP_TRY(hipEventCreate(&e));
+    }
+    HIP_TRY(hipEventRecord(r->ev0, r->stream));
+    if (r->graph) {
+        HIP_TRY(hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal));
+        rc = dispatch_launch(r, d, ld, n_chunks);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(r->cap, &g);
+        if (rc != SSA_OK)
+            return rc;
+        if (ec != hipSuccess)
+            return fail(SSA_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        r->g = g;
+        HIP_TRY(hipGraphInstantiate(&r->gx, r->g, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphLaunch(r->gx, r->stream));
+    } else {
+        rc = dispatch_launch(r, d, ld, n_chunks);
+        if (rc != SSA_OK)
+            return rc;
+    }
+    HIP_TRY(hipEventRecord(r->ev1, r->stream));
+    return SSA_OK;
+}
+
+void release(ssa_run *r)
+{
+    if (!r)
+        return;
+    if (r->ev1)
+        (void)hipEventSynchronize(r->ev1);
+    else
+        (void)hipStreamSynchronize(r->stream);
+    if (r->gx)
+        (void)hipGraphExecDestroy(r->gx);
+    if (r->g)
+        (void)hipGraphDestroy(r->g);
+    if (r->cap)
+        (void)hipStreamDestroy(r->cap);
+    for (auto e : r->kev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (r->ev0)
+        (void)hipEventDestroy(r->ev0);
+    if (r->ev1)
+        (void)hipEventDestroy(r->ev1);
+    for (void *p : r->owned)
+        (void)hipFree(p);
+    delete r;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+int ssa_model_create(int32_t n_species, int32_t n_reactions, const int32_t *reactant_order,
+                     const int32_t *stoich, const ssa_law *laws, ssa_model **out)
+{
+    if (!out)
+        return fail(SSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_species < 1 || n_species > kMaxSpecies)
+        return fail(SSA_E_INVALID, "n_species must be in [1, 32]");
+    if (n_reactions < 1 || n_reactions > kMaxReactions)
+        return fail(SSA_E_INVALID, "n_reactions must be in [1, 64]");
+    if (!reactant_order || !stoich || !laws)
+        return fail(SSA_E_INVALID, "reactant_order, stoich and laws must be non-NULL");
+    const int N = n_species, M = n_reactions;
+    for (int j = 0; j < M; ++j) {
+        const ssa_law &L = laws[j];
+        if (!(L.k >= 0.0) || !std::isfinite(L.k))
+            return fail(SSA_E_INVALID, "rate constant k must be finite and >= 0 (reaction " + std::to_string(j) + ")");
+        if (L.kind == SSA_LAW_MASS_ACTION) {
+            int tot = 0;
+            for (int s = 0; s < N; ++s) {
+                int o = reactant_order[(size_t)j * N + s];
+                if (o < 0)
+                    return fail(SSA_E_INVALID, "reactant orders must be >= 0");
+                tot += o;
+            }
+            if (tot > kMaxOrder)
+                return fail(SSA_E_UNSUPPORTED, "total reaction order above 4");
+        } else if (L.kind == SSA_LAW_HILL_REPRESS || L.kind == SSA_LAW_HILL_ACTIVATE) {
+            if (L.regulator < 0 || L.regulator >= N)
+                return fail(SSA_E_INVALID, "Hill regulator out of range");
+            if (L.h < 1 || L.h > 8)
+                return fail(SSA_E_INVALID, "Hill exponent must be in [1, 8]");
+            if (!(L.K > 0.0) || !std::isfinite(L.K))
+                return fail(SSA_E_INVALID, "Hill K must be finite and > 0");
+            if (!(L.basal >= 0.0) || !std::isfinite(L.basal))
+                return fail(SSA_E_INVALID, "Hill basal rate must be finite and >= 0");
+        } else {
+            return fail(SSA_E_INVALID, "unknown law kind");
+        }
+        for (int s = 0; s < N; ++s) {
+            int v = stoich[(size_t)j * N + s];
+            if (v < -1024 || v > 1024)
+                return fail(SSA_E_INVALID, "stoichiometric entries must be in [-1024, 1024]");
+        }
+    }
+    ssa_model *m = new (std::nothrow) ssa_model;
+    if (!m)
+        return fail(SSA_E_NOMEM, "out of host memory");
+    m->m.N = N;
+    m->m.M = M;
+    m->m.order.assign(reactant_order, reactant_order + (size_t)M * N);
+    m->m.nu.assign(stoich, stoich + (size_t)M * N);
+    m->m.law.assign(laws, laws + M);
+    for (int j = 0; j < M; ++j)
+        if (m->m.law[j].kind != SSA_LAW_MASS_ACTION)
+            for (int s = 0; s < N; ++s)
+                m->m.order[(size_t)j * N + s] = 0;
+    *out = m;
+    return SSA_OK;
+}
+
+void ssa_model_destroy(ssa_model *model) { delete model; }
+
+int ssa_ensemble_run(const ssa_run_desc *desc, ssa_run **out)
+{
+    if (!out)
+        return fail(SSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    ssa_run *r = new (std::nothrow) ssa_run;
+    if (!r)
+        return fail(SSA_E_NOMEM, "out of host memory");
+    rc = run_impl(desc, r);
+    if (rc != SSA_OK) {
+        std::string keep = g_err;
+        release(r);
+        g_err = keep;
+        return rc;
+    }
+    *out = r;
+    return SSA_OK;
+}
+
+int ssa_run_wait(ssa_run *run)
+{
+    if (!run)
+        return fail(SSA_E_INVALID, "run is NULL");
+    HIP_TRY(hipEventSynchronize(run->ev1));
+    return SSA_OK;
+}
+
+int ssa_snapshots_get(const ssa_run *run, int32_t item, int32_t *dst, size_t dst_elems, int dst_is_device)
+{
+    if (!run || item < 0 || item >= (int)run->items.size())
+        return fail(SSA_E_INVALID, "run is NULL or item out of range");
+    const ItemBuf &b = run->items[item];
+    size_t n = (size_t)run->K * b.N * b.E;
+    if (dst_elems != n)
+        return fail(SSA_E_INVALID, "dst_elems must equal n_snap * n_species * n_traj");
+    if (n == 0)
+        return SSA_OK;
+    if (!dst)
+        return fail(SSA_E_INVALID, "dst is NULL");
+    HIP_TRY(hipEventSynchronize(run->ev1));
+    HIP_TRY(hipMemcpy(dst, b.snap, n * sizeof(int32_t), dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return SSA_OK;
+}
+
+int ssa_run_stats_get(const ssa_run *run, int32_t item, uint64_t *n_events, double *t_last, uint8_t *status,
+                      int dst_is_device)
+{
+    if (!run || item < 0 || item >= (int)run->items.size())
+        return fail(SSA_E_INVALID, "run is NULL or item out of range");
+    const ItemBuf &b = run->items[item];
+    const size_t E = (size_t)b.E;
+    if (E == 0)
+        return SSA_OK;
+    HIP_TRY(hipEventSynchronize(run->ev1));
+    hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (n_events)
+        HIP_TRY(hipMemcpy(n_events, b.nev, E * sizeof(uint64_t), kind));
+    if (t_last)
+        HIP_TRY(hipMemcpy(t_last, b.tlast, E * sizeof(double), kind));
+    if (status)
+        HIP_TRY(hipMemcpy(status, b.status, E * sizeof(uint8_t), kind));
+    return SSA_OK;
+}
+
+int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
+{
+    if (!run || !info)
+        return fail(SSA_E_INVALID, "run and info must be non-NULL");
+    HIP_TRY(hipEventSynchronize(run->ev1));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, run->ev0, run->ev1));
+    info->elapsed_ms = ms;
+    double kms = 0.0;
+    if (!run->graph) {
+        for (int c = 0; c < run->n_launch; ++c) {
+            float m = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&m, run->kev[2 * c], run->kev[2 * c + 1]));
+            kms += m;
+        }
+    } else {
+        kms = ms;
+    }
+    info->kernel_ms = kms;
+    info->n_launches = run->n_launch;
+    info->block_size = run->block;
+    info->grid_size = run->grid;
+    info->vgprs = run->vgprs;
+    uint64_t tot = 0;
+    for (const ItemBuf &b : run->items) {
+        if (b.E == 0)
+            continue;
+        std::vector<uint64_t> h((size_t)b.E);
+        HIP_TRY(hipMemcpy(h.data(), b.nev, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        for (uint64_t v : h)
+            tot += v;
+    }
+    info->total_events = tot;
+    return SSA_OK;
+}
+
+void ssa_run_destroy(ssa_run *run) { release(run); }
+
+const char *ssa_last_error(void) { return g_err.c_str(); }
+
+const char *ssa_version(void) { return "ssa_rp 0.1 (gfx950)"; }
+
+// Compile (and cache on disk) the kernel a run with this descriptor would use,
+// without touching a GPU. Used by the build step to fill the kernel cache.
+int ssa_prepare(const ssa_run_desc *desc)
+{
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    std::string src;
+    build_source(desc, src);
+    std::vector<char> code;
+    return compile_source(src, "gfx950", code);
+}
+
+// Write the generated kernel source for a descriptor to `path` (inspection).
+int ssa_dump_source(const ssa_run_desc *desc, const char *path)
+{
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    std::string src;
+    build_source(desc, src);
+    std::ofstream out(path);
+    if (!out)
+        return fail(SSA_E_INVALID, "cannot open path");
+    out << src;
+    return SSA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,552 @@
+// ssa_device.hip - device side of the ensemble direct method on gfx950.
+//
+// This file is compiled at run time by hipRTC together with a short,
+// generated description of the reaction networks in the launch (species and
+// reaction counts, the op sequence of every propensity, the net-change table)
+// and one instantiation line. Everything structural is therefore a
+// compile-time constant: propensity evaluation, prefix sums, selection and the
+// integer update are straight-line code in registers, one trajectory per lane.
+// Rate constants, initial states, horizons and snapshot grids stay runtime data.
+//
+// Method (Kimpson, Flegg & Flegg, Sec. 2, Direct Method steps 1-4):
+//   a_j(x), a0 = sum a_j;  tau = -ln(u1)/a0;  mu = min{j : S_j > u2 a0};
+//   x += nu_mu, t += tau.
+// Precision partition (Sec. 3.2 and opening of Sec. 4):
+//   FP64 / FP32: every op in that type.
+//   mixed T16:   propensity ops in fp16/bf16, sums, tau, time in binary32.
+//   uniform T16: every op in fp16/bf16, including the clock.
+// Stochastic rounding (Sec. 3.3): each 16-bit op rounds its binary32 result
+// up with probability (x - x-)/(x+ - x-), decided by a 16-bit halfword.
+//
+// Random bits: Philox4x32-10, key = seed, counter = (event lo, event hi,
+// trajectory id, stream). Stream 0 gives the two uniforms (53-bit pairs in
+// FP64, 24-bit words otherwise) and, in SR modes, rounding halfwords 0..3;
+// stream q supplies halfwords 4+8(q-1) .. 11+8(q-1). Every rounding op of an
+// event owns a fixed halfword slot, so a step's randomness is a function of
+// (seed, trajectory, event) only and results do not depend on lane scheduling.
+#pragma clang fp contract(off)
+
+typedef unsigned int u32;
+typedef int i32;
+typedef unsigned long long u64;
+typedef long long i64;
+
+#define SSA_INF_F __builtin_inff()
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// --------------------------------------------------------------------------
+struct W4 {
+    u32 w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ W4 philox10(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        u64 p0 = (u64)0xD2511F53u * (u64)c0;
+        u64 p1 = (u64)0xCD9E8D57u * (u64)c2;
+        u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0;
+        u32 n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (u32)p1;
+        c3 = (u32)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    W4 o = {c0, c1, c2, c3};
+    return o;
+}
+
+// --------------------------------------------------------------------------
+// Uniforms on (0, 1]: (m + 1) 2^-53 from 53 bits, (m + 1) 2^-24 from 24 bits.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double unif53(u32 a, u32 b)
+{
+    u64 m = ((u64)a << 21) | (u64)(b >> 11);
+    return (double)(m + 1ull) * 0x1p-53;
+}
+
+__device__ __forceinline__ float unif24(u32 w)
+{
+    return (float)((w >> 8) + 1u) * 0x1p-24f;
+}
+
+// --------------------------------------------------------------------------
+// -ln(u), u in (0, 1]: u = 2^e f with f in [1/sqrt2, sqrt2],
+// ln f = 2 atanh(s) = 2s (1 + s^2/3 + s^4/5 + ...), s = (f - 1)/(f + 1),
+// e ln2 with ln2 split in a short high part (exact product) and a low part.
+// Only correctly rounded +, -, *, / are used, in a fixed order.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double neg_log64(double u)
+{
+    u64 bits = (u64)__double_as_longlong(u);
+    int e = (int)((bits >> 52) & 0x7FFull) - 1023;
+    double f = __longlong_as_double((i64)((bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull));
+    if (f > 0x1.6a09e667f3bcdp+0) {
+        f = f * 0.5;
+        e = e + 1;
+    }
+    double s = (f - 1.0) / (f + 1.0);
+    double z = s * s;
+    double p = 0x1.8618618618618p-5;          // 1/21
+    p = p * z + 0x1.af286bca1af28p-5;         // 1/19
+    p = p * z + 0x1.e1e1e1e1e1e1ep-5;         // 1/17
+    p = p * z + 0x1.1111111111111p-4;         // 1/15
+    p = p * z + 0x1.3b13b13b13b14p-4;         // 1/13
+    p = p * z + 0x1.745d1745d1746p-4;         // 1/11
+    p = p * z + 0x1.c71c71c71c71cp-4;         // 1/9
+    p = p * z + 0x1.2492492492492p-3;         // 1/7
+    p = p * z + 0x1.999999999999ap-3;         // 1/5
+    p = p * z + 0x1.5555555555555p-2;         // 1/3
+    p = p * z;
+    double s2 = s + s;
+    double lnf = s2 + s2 * p;
+    double ed = (double)e;
+    double r = ed * 0x1.62e42fep-1 + (ed * 0x1.f473de6af278fp-30 + lnf);
+    return 0.0 - r;
+}
+
+__device__ __forceinline__ float neg_log32(float u)
+{
+    u32 bits = __float_as_uint(u);
+    int e = (int)((bits >> 23) & 0xFFu) - 127;
+    float f = __uint_as_float((bits & 0x7FFFFFu) | 0x3F800000u);
+    if (f > 0x1.6a09e6p+0f) {
+        f = f * 0.5f;
+        e = e + 1;
+    }
+    float s = (f - 1.0f) / (f + 1.0f);
+    float z = s * s;
+    float p = 0x1.c71c72p-4f;                 // 1/9
+    p = p * z + 0x1.24924ap-3f;               // 1/7
+    p = p * z + 0x1.99999ap-3f;               // 1/5
+    p = p * z + 0x1.555556p-2f;               // 1/3
+    p = p * z;
+    float s2 = s + s;
+    float lnf = s2 + s2 * p;
+    float ed = (float)e;
+    float r = ed * 0x1.62e4p-1f + (ed * 0x1.7f7d1cp-20f + lnf);
+    return 0.0f - r;
+}
+
+// --------------------------------------------------------------------------
+// Rounding a binary32 value to fp16 / bf16 (result carried as binary32).
+// Formats per Table tab:formats: fp16 has 11 significand bits and normals
+// from 2^-14; bf16 keeps binary32's exponent range with 8 significand bits.
+// RNE uses the hardware conversions (IEEE round-to-nearest-even with
+// subnormals kept, overflow to infinity). SR rounds the magnitude up iff the
+// halfword rb is below floor(2^16 * fraction of a grid step dropped).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float rne_f16(float v)
+{
+    return (float)(_Float16)v;
+}
+
+__device__ __forceinline__ float rne_bf16(float v)
+{
+    u32 b = __float_as_uint(v);
+    b = b + 0x7FFFu + ((b >> 16) & 1u);
+    return __uint_as_float(b & 0xFFFF0000u);
+}
+
+__device__ __forceinline__ float sr_bf16(float v, u32 rb)
+{
+    u32 b = __float_as_uint(v);
+    u32 up = rb < (b & 0xFFFFu) ? 0x10000u : 0u;
+    return __uint_as_float((b & 0xFFFF0000u) + up);
+}
+
+__device__ __forceinline__ float sr_f16(float v, u32 rb)
+{
+    u32 b = __float_as_uint(v);
+    u32 mag = b & 0x7FFFFFFFu;
+    u32 sgn = b & 0x80000000u;
+    if (mag >= 0x47800000u)                    // |v| >= 2^16, inf or NaN
+        return mag > 0x7F800000u ? v : __uint_as_float(sgn | 0x7F800000u);
+    if (mag >= 0x38800000u) {                  // fp16 normal range, 13 bits dropped
+        u32 up = rb < ((mag & 0x1FFFu) << 3) ? 0x2000u : 0u;
+        u32 r = (mag & ~0x1FFFu) + up;
+        if (r >= 0x47800000u)
+            r = 0x7F800000u;
+        return __uint_as_float(sgn | r);
+    }
+    // fp16 subnormal range: grid step 2^-24
+    float q = __uint_as_float(mag) * 0x1p24f;
+    float fl = __builtin_floorf(q);
+    u32 thr = (u32)((q - fl) * 65536.0f);
+    float r = (fl + (rb < thr ? 1.0f : 0.0f)) * 0x1p-24f;
+    return __uint_as_float(sgn | __float_as_uint(r));
+}
+
+// --------------------------------------------------------------------------
+// Precision policies. T: propensity type; A: sum/target type; Tm: clock type.
+// rnd(v, rb) is the one rounding applied after every 16-bit op.
+// --------------------------------------------------------------------------
+enum { FMT_FP64 = 0, FMT_FP32 = 1, FMT_FP16 = 2, FMT_BF16 = 3 };
+
+struct PrecF64 {
+    typedef double T;
+    typedef double A;
+    typedef double Tm;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true;
+    __device__ static T cvt(i32 v, u32) { return (double)v; }
+    __device__ static T mul(T a, T b, u32) { return a * b; }
+    __device__ static T div(T a, T b, u32) { return a / b; }
+    __device__ static T add(T a, T b, u32) { return a + b; }
+    __device__ static A acc(A s, T a, u32) { return s + (A)a; }
+    __device__ static A arnd(A v, u32) { return v; }
+};
+
+struct PrecF32 {
+    typedef float T;
+    typedef float A;
+    typedef float Tm;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false;
+    __device__ static T cvt(i32 v, u32) { return (float)v; }
+    __device__ static T mul(T a, T b, u32) { return a * b; }
+    __device__ static T div(T a, T b, u32) { return a / b; }
+    __device__ static T add(T a, T b, u32) { return a + b; }
+    __device__ static A acc(A s, T a, u32) { return s + a; }
+    __device__ static A arnd(A v, u32) { return v; }
+};
+
+template <int FMT, bool SRM>
+__device__ __forceinline__ float rnd16(float v, u32 rb)
+{
+    if constexpr (FMT == FMT_FP16)
+        return SRM ? sr_f16(v, rb) : rne_f16(v);
+    else
+        return SRM ? sr_bf16(v, rb) : rne_bf16(v);
+}
+
+template <int FMT, bool SRM, bool UNIF, bool NRM>
+struct Prec16 {
+    typedef float T;
+    typedef float A;
+    typedef float Tm;
+    static constexpr bool SR = SRM, UNI = UNIF, NORM = NRM, WIDE = false;
+    __device__ static T cvt(i32 v, u32 rb) { return rnd16<FMT, SRM>((float)v, rb); }
+    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a * b, rb); }
+    __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a / b, rb); }
+    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a + b, rb); }
+    __device__ static A acc(A s, T a, u32 rb) { return UNIF ? rnd16<FMT, SRM>(s + a, rb) : s + a; }
+    __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SRM>(v, rb) : v; }
+};
+
+// --------------------------------------------------------------------------
+// Rounding-halfword pool of one event: words 2, 3 of the stream-0 draw, then
+// four words from each further stream. Slot s is half (s & 1) of word s >> 1.
+// --------------------------------------------------------------------------
+template <int NSLOT>
+struct Pool {
+    static constexpr int NSTREAM = NSLOT <= 4 ? 1 : 1 + (NSLOT - 4 + 7) / 8;
+    static constexpr int NW = NSLOT <= 0 ? 1 : 2 + 4 * (NSTREAM - 1);
+    u32 w[NW];
+    // slots past the pool belong to ops that do not round stochastically
+    __device__ __forceinline__ u32 hw(int s) const
+    {
+        if (s >= 2 * NW)
+            return 0u;
+        return (s & 1) ? (w[s >> 1] >> 16) : (w[s >> 1] & 0xFFFFu);
+    }
+};
+
+// --------------------------------------------------------------------------
+// Launch arguments.
+// --------------------------------------------------------------------------
+struct ItemArgs {
+    const void *rates;       // [n_sets][M] constants in the mode's type (T)
+    const void *hill;        // [M][2] (b_j, K_j) in T, Hill reactions only
+    const i32 *x0;           // [N]
+    i32 *snap;               // [k_hi - k_lo][N][E] snapshot rows of this launch
+    u64 *n_events;           // [E]
+    double *t_last;          // [E]
+    unsigned char *status;   // [E]; 255 = suspended at a chunk boundary
+    i32 *cx;                 // carry [N][E] (chunked runs)
+    double *ct;              // carry clock [E]
+    u64 *cn;                 // carry event index [E]
+    i32 *ck;                 // carry next snapshot index [E]
+    float *cm;               // carry running maximum [E]
+    u32 *counter;            // work counter of this item (starts at 0)
+    u32 E;                   // trajectories
+    u32 traj_per_set;        // trajectories per rate set (0: one set)
+    u32 id_base;             // Philox trajectory id of trajectory 0
+    u32 pad;
+};
+
+struct LaunchArgs {
+    const double *snap_t64;  // [K]
+    const float *snap_t32;   // [K]
+    double t_end64;
+    float t_end32;
+    i32 K;
+    i32 k_lo, k_hi;          // snapshot rows written by this launch
+    i32 first, last;         // first / last chunk of the run
+    u32 seed_lo, seed_hi;
+    u64 max_events;          // 0 = no cap
+    ItemArgs item[SSA_N_ITEMS];
+};
+
+enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
+
+__device__ __forceinline__ u32 lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ u32 rank_in(u64 mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+template <class P>
+__device__ __forceinline__ typename P::Tm snap_time(const LaunchArgs &L, int k)
+{
+    if constexpr (P::WIDE)
+        return L.snap_t64[k];
+    else
+        return L.snap_t32[k];
+}
+
+// --------------------------------------------------------------------------
+// One wave works through one item: lanes claim trajectories from the item's
+// counter, run events, and claim again as they finish (ballot + prefix rank,
+// one atomic per refill), until the counter passes E and every lane is idle.
+// Md: generated network description; P: precision policy.
+// --------------------------------------------------------------------------
+template <class P, class Md, bool PER_LANE_RATES>
+__device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
+{
+    typedef typename P::T T;
+    typedef typename P::A A;
+    typedef typename P::Tm Tm;
+    constexpr int N = Md::N, M = Md::M;
+    constexpr int NSLOT = P::SR ? (Md::NPROP + (P::UNI ? (P::NORM ? 2 * M + 4 : M + 3) : 0)) : 0;
+    constexpr int SLOT_NORM = Md::NPROP;
+    constexpr int SLOT_SUM = Md::NPROP + (P::NORM ? M : 0);
+    constexpr int SLOT_LOG = SLOT_SUM + M - 1;
+    constexpr int SLOT_TAU = SLOT_LOG + 1;
+    constexpr int SLOT_TAUM = SLOT_TAU + 1;
+    constexpr int SLOT_TIME = SLOT_TAU + 1 + (P::NORM ? 1 : 0);
+    constexpr int SLOT_TARGET = SLOT_TIME + 1;
+
+    const T *rates = (const T *)I.rates;
+    const T *hill = (const T *)I.hill;
+    const Tm t_end = P::WIDE ? (Tm)L.t_end64 : (Tm)L.t_end32;
+    const u32 lane = lane_id();
+
+    i32 x[N];
+    T c[M];
+    Tm t = 0;
+    u64 n = 0;
+    i32 k = 0;
+    float mrun = 0.0f;
+    u32 idx = 0;
+    bool active = false;
+    bool open = true;
+
+    if constexpr (!PER_LANE_RATES) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            c[j] = rates[j];
+    }
+
+    for (;;) {
+        if (open) {
+            u64 need = __ballot(!active);
+            if (need) {
+                u32 cnt = (u32)__popcll(need);
+                u32 leader = (u32)__ffsll((long long)need) - 1u;
+                u32 base = 0;
+                if (lane == leader)
+                    base = atomicAdd(I.counter, cnt);
+                base = __builtin_amdgcn_readlane(base, leader);
+                if (!active) {
+                    u32 id = base + rank_in(need);
+                    if (id < I.E) {
+                        idx = id;
+                        active = true;
+                        if constexpr (PER_LANE_RATES) {
+                            u32 set = I.traj_per_set ? id / I.traj_per_set : 0u;
+#pragma unroll
+                            for (int j = 0; j < M; ++j)
+                                c[j] = rates[(u64)set * M + j];
+                        }
+                        if (L.first) {
+#pragma unroll
+                            for (int s = 0; s < N; ++s)
+                                x[s] = I.x0[s];
+                            t = 0;
+                            n = 0;
+                            k = 0;
+                            mrun = 0.0f;
+                        } else {
+#pragma unroll
+                            for (int s = 0; s < N; ++s)
+                                x[s] = I.cx[(u64)s * I.E + id];
+                            t = (Tm)I.ct[id];
+                            n = I.cn[id];
+                            k = I.ck[id];
+                            mrun = I.cm[id];
+                            if (I.status[id] != ST_SUSPENDED) {
+                                // finished in an earlier chunk: fill this chunk's rows
+                                for (int kk = L.k_lo; kk < L.k_hi; ++kk)
+#pragma unroll
+                                    for (int s = 0; s < N; ++s)
+                                        I.snap[((u64)(kk - L.k_lo) * N + s) * I.E + id] = x[s];
+                                active = false;
+                            }
+                        }
+                    }
+                }
+                if (base + cnt >= I.E)
+                    open = false;
+            }
+        }
+        u64 act = __ballot(active);
+        if (act == 0) {
+            if (!open)
+                break;
+            continue;
+        }
+
+        for (;;) {
+            if (active) {
+                int status = -1;
+                // ---- random draws for event n
+                const u32 id = I.id_base + idx;
+                W4 r0 = philox10((u32)n, (u32)(n >> 32), id, 0u, L.seed_lo, L.seed_hi);
+                Pool<NSLOT> pool;
+                if constexpr (NSLOT > 0) {
+                    pool.w[0] = r0.w2;
+                    pool.w[1] = r0.w3;
+#pragma unroll
+                    for (int q = 1; q < Pool<NSLOT>::NSTREAM; ++q) {
+                        W4 rq = philox10((u32)n, (u32)(n >> 32), id, (u32)q, L.seed_lo, L.seed_hi);
+                        pool.w[2 + 4 * (q - 1) + 0] = rq.w0;
+                        pool.w[2 + 4 * (q - 1) + 1] = rq.w1;
+                        pool.w[2 + 4 * (q - 1) + 2] = rq.w2;
+                        pool.w[2 + 4 * (q - 1) + 3] = rq.w3;
+                    }
+                }
+                A u1, u2;
+                if constexpr (P::WIDE) {
+                    u1 = unif53(r0.w0, r0.w1);
+                    u2 = unif53(r0.w2, r0.w3);
+                } else {
+                    u1 = unif24(r0.w0);
+                    u2 = unif24(r0.w1);
+                }
+                // ---- propensities (generated op sequence)
+                T a[M];
+                Md::template propensities<P>(x, c, hill, a, pool);
+                // ---- optional running-max normalisation (uniform 16-bit)
+                T m = (T)1;
+                bool bad = false;
+                if constexpr (P::NORM) {
+                    float mx = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        mx = a[j] > mx ? a[j] : mx;
+                    mrun = mx > mrun ? mx : mrun;
+                    if (!(mrun <= 3.40282347e38f)) {
+                        status = ST_OVERFLOW;
+                        bad = true;
+                    } else if (!(mrun > 0.0f)) {
+                        status = ST_ABSORBED;
+                        bad = true;
+                    }
+                    m = mrun;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        a[j] = P::div(a[j], m, pool.hw(SLOT_NORM + j));
+                }
+                // ---- partial sums and total
+                A S[M];
+                S[0] = (A)a[0];
+#pragma unroll
+                for (int j = 1; j < M; ++j)
+                    S[j] = P::acc(S[j - 1], a[j], pool.hw(SLOT_SUM + j - 1));
+                const A a0 = S[M - 1];
+                if (!bad) {
+                    if (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f)))
+                        status = ST_OVERFLOW;
+                    else if (!(a0 > (A)0))
+                        status = ST_ABSORBED;
+                }
+                if (status < 0) {
+                    // ---- waiting time and clock
+                    Tm t_new;
+                    if constexpr (P::WIDE) {
+                        t_new = t + neg_log64(u1) / a0;
+                    } else if constexpr (P::UNI) {
+                        A lg = P::arnd(neg_log32(u1), pool.hw(SLOT_LOG));
+                        A tau = P::arnd(lg / a0, pool.hw(SLOT_TAU));
+                        if constexpr (P::NORM)
+                            tau = P::arnd(tau / m, pool.hw(SLOT_TAUM));
+                        t_new = P::arnd(t + tau, pool.hw(SLOT_TIME));
+                    } else {
+                        t_new = t + neg_log32(u1) / a0;
+                    }
+                    // ---- snapshots strictly before t_new hold the current state
+                    while (k < L.k_hi && snap_time<P>(L, k) < t_new) {
+#pragma unroll
+                        for (int s = 0; s < N; ++s)
+                            I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
+                        ++k;
+                    }
+                    if (t_new > t_end) {
+                        status = ST_DONE;
+                    } else if (!L.last && k >= L.k_hi) {
+                        status = ST_SUSPENDED;   // event n is redone by the next chunk
+                    } else {
+                        // ---- selection and integer update
+                        A target = P::arnd(u2 * a0, pool.hw(SLOT_TARGET));
+                        int mu = 0;
+#pragma unroll
+                        for (int j = 0; j < M; ++j)
+                            mu += (S[j] <= target) ? 1 : 0;
+                        if (mu == M) {
+                            mu = 0;
+#pragma unroll
+                            for (int j = 0; j < M; ++j)
+                                mu = (a[j] > (T)0) ? j : mu;
+                        }
+                        Md::update(x, mu);
+                        t = t_new;
+                        ++n;
+                        if (L.max_events && n == L.max_events)
+                            status = ST_CAPPED;
+                    }
+                }
+                if (status >= 0) {
+                    // ---- finish (or suspend) this trajectory
+                    if (status != ST_SUSPENDED) {
+                        for (; k < L.k_hi; ++k)
+#pragma unroll
+                            for (int s = 0; s < N; ++s)
+                                I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
+                        I.n_events[idx] = n;
+                        I.t_last[idx] = (double)t;
+                    }
+                    I.status[idx] = (unsigned char)status;
+                    if (!L.last) {
+#pragma unroll
+                        for (int s = 0; s < N; ++s)
+                            I.cx[(u64)s * I.E + idx] = x[s];
+                        I.ct[idx] = (double)t;
+                        I.cn[idx] = n;
+                        I.ck[idx] = k;
+                        I.cm[idx] = mrun;
+                    }
+                    active = false;
+                }
+            }
+            u64 now = __ballot(active);
+            if (now == 0 || (open && now != act))
+                break;
+        }
+    }
+}

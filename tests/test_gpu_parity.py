@@ -1,0 +1,185 @@
+"""GPU path vs oracle, trajectory by trajectory, through the C ABI.
+
+The bar: species counts, event counts and statuses bit-exact; the time of the
+last event within 1e-12 relative (FP64) or 1e-6 relative (binary32 clocks).
+Sizes are chosen so the oracle finishes in seconds while the launch still
+spans many waves, ragged tails and the lane-refill path; the full-size
+Schloegl ensemble is checked on a sample of trajectory ids.
+"""
+import numpy as np
+import pytest
+
+from paper_2605_00479_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+ORACLE_THREADS = 16
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_2605_00479_amd import ssa
+    ssa.lib()
+    return ssa
+
+
+def tol_for(mode):
+    return 1e-12 if mode == "FP64" else 1e-6
+
+
+def assert_parity(orc_res, snap, stats, mode, label=""):
+    np.testing.assert_array_equal(snap, orc_res["snap"], err_msg=f"snapshots {label} {mode}")
+    np.testing.assert_array_equal(stats["status"], orc_res["status"], err_msg=f"status {label} {mode}")
+    np.testing.assert_array_equal(stats["n_events"], orc_res["n_events"], err_msg=f"events {label} {mode}")
+    a, b = stats["t_last"], orc_res["t_last"]
+    rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+    assert np.all((a == b) | (rel <= tol_for(mode))), f"t_last {label} {mode}: max rel {rel.max()}"
+
+
+def run_both(gpu, orc, spec, x0, n, t_end, snap_t, mode, *, seed=1, max_events=0, set_rate=None,
+             traj_per_set=0, indices=None, **launch):
+    m = gpu.Model(spec)
+    item = {"model": m, "x0": x0, "n_traj": n}
+    if set_rate is not None:
+        item["set_rates"] = set_rate
+        item["traj_per_set"] = traj_per_set
+    print(f"[gpu-parity] {spec.name} mode={mode} n={n} seed={seed} launch={launch}", flush=True)
+    run = gpu.ssa_ensemble_run([item], t_end, snap_t, seed, mode, max_events=max_events, **launch)
+    snap = run.snapshots(0)
+    st = run.stats(0)
+    idx = np.arange(n) if indices is None else np.asarray(indices)
+    ref = orc.simulate(spec, mode, x0, t_end, snap_t, seed, indices=idx, max_events=max_events,
+                       set_rate=set_rate, traj_per_set=traj_per_set, threads=ORACLE_THREADS)
+    st = {k: v[idx] for k, v in st.items()}
+    assert_parity(ref, snap[:, :, idx], st, mode, spec.name)
+    return run, snap, st
+
+
+def test_birth_death_config_fp64(gpu, orc):
+    W = wl.config_birth_death()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, it.n_traj, W.t_end, W.snap_t, "FP64", seed=W.seed)
+
+
+@pytest.mark.parametrize("mode", ["FP64", "FP32", "MIX_F16_RTN", "MIX_F16_SR", "MIX_BF16_RTN", "MIX_BF16_SR"])
+def test_schlogl_modes(gpu, orc, mode):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, 1500, W.t_end, W.snap_t, mode, seed=W.seed, max_events=W.max_events)
+
+
+@pytest.mark.parametrize("mode", ["UNI_F16_RTN", "UNI_F16_SR", "UNI_F16_SR_NORM", "UNI_BF16_RTN",
+                                  "UNI_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_RTN_NORM", "FP64"])
+def test_telegraph_uniform_modes(gpu, orc, mode):
+    W = wl.config_telegraph()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, 1000, 60.0, wl.snapshot_grid(60.0, 61), mode, seed=W.seed,
+             max_events=W.max_events)
+
+
+@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR", "MIX_BF16_SR", "UNI_F16_SR"])
+def test_repressilator_hill_laws(gpu, orc, mode):
+    m = wl.repressilator()
+    run_both(gpu, orc, m, np.array([0, 0, 0, 0, 0, 20], np.int32), 600, 60.0, wl.snapshot_grid(60.0, 61),
+             mode, seed=3, max_events=10_000_000)
+
+
+@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR"])
+def test_dimer_parameter_sets_per_lane(gpu, orc, mode):
+    rates = wl.dimer_sweep_rates(48)
+    m = wl.dimer_open()
+    run_both(gpu, orc, m, np.array([0, 0], np.int32), 48 * 40, 10.0, wl.snapshot_grid(10.0, 11), mode,
+             seed=1, set_rate=rates, traj_per_set=40, max_events=3_000_000)
+
+
+def test_self_repressor_activation_and_repression(gpu, orc):
+    spec = wl._build("hill_pair", ["X", "Y"], [
+        {"change": {"X": +1}, "hill": ("repress", "Y", 1.0, 40.0, 15.0, 3)},
+        {"reactants": {"X": 1}, "change": {"X": -1}, "k": 1.0},
+        {"change": {"Y": +1}, "hill": ("activate", "X", 0.5, 30.0, 20.0, 2)},
+        {"reactants": {"Y": 1}, "change": {"Y": -1}, "k": 0.7},
+    ])
+    for mode in ("FP64", "FP32", "MIX_BF16_SR", "UNI_F16_SR_NORM"):
+        run_both(gpu, orc, spec, np.array([3, 0], np.int32), 700, 20.0, wl.snapshot_grid(20.0, 9), mode, seed=9)
+
+
+def test_refill_path_single_workgroup(gpu, orc):
+    """One workgroup of one wave runs 2,000 trajectories: every lane refills
+    many times from the work counter."""
+    W = wl.config_birth_death()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, 2000, 20.0, [5.0, 20.0], "MIX_F16_SR", seed=4,
+             block_size=64, grid_size=1)
+
+
+def test_ragged_and_tiny_ensembles(gpu, orc):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    for n in (1, 63, 65, 257):
+        run_both(gpu, orc, it.model, it.x0, n, 1.0, wl.snapshot_grid(1.0, 5), "MIX_F16_SR", seed=5)
+
+
+def test_chunked_graph_run_matches_single_launch(gpu, orc):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    for mode in ("FP64", "UNI_BF16_SR_NORM"):
+        _, s1, st1 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
+                              max_events=W.max_events)
+        _, s4, st4 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
+                              max_events=W.max_events, n_chunks=4)
+        np.testing.assert_array_equal(s1, s4)
+        for k in st1:
+            np.testing.assert_array_equal(st1[k], st4[k])
+
+
+def test_special_statuses(gpu, orc):
+    # absorbing: pure decay from 5
+    run_both(gpu, orc, wl.birth_death(0.0, 1.0), np.array([5], np.int32), 300, 1e6, [0.0, 1e6], "FP64")
+    # fp16 overflow at event 0 (zero-order constant 1e5 > 65504)
+    _, s, st = run_both(gpu, orc, wl.birth_death(1e5, 1.0), np.array([250], np.int32), 130, 10.0,
+                        [0.0, 5.0, 10.0], "MIX_F16_SR")
+    assert np.all(st["status"] == 2) and np.all(s == 250)
+    # event cap under uniform bf16 RTN
+    _, _, st = run_both(gpu, orc, wl.birth_death(10.0, 0.1), np.array([0], np.int32), 200, 100.0,
+                        [50.0, 100.0], "UNI_BF16_RTN", max_events=300)
+    assert np.all(st["status"] == 3)
+
+
+def test_no_snapshots_and_empty_item(gpu, orc):
+    m = wl.birth_death()
+    run_both(gpu, orc, m, np.array([0], np.int32), 100, 3.0, [], "FP64")
+    mdl = gpu.Model(m)
+    run = gpu.ssa_ensemble_run([{"model": mdl, "x0": [0], "n_traj": 0}], 3.0, [1.0], 1, "FP64")
+    assert run.snapshots(0).shape == (1, 1, 0)
+
+
+def test_multi_item_batch_matches_oracle_per_item(gpu, orc):
+    """Five networks in one persistent launch; item m's trajectory ids start
+    after the previous items' (traj_id_base + offset)."""
+    W = wl.config_heterogeneous(n_traj_total=5 * 150)
+    t_end, ts = 15.0, wl.snapshot_grid(15.0, 16)
+    models = {}
+    items = gpu.items_from_workload(W, models)
+    for mode in ("FP64", "MIX_F16_SR", "MIX_BF16_SR"):
+        print(f"[gpu-parity] heterogeneous mode={mode}", flush=True)
+        run = gpu.ssa_ensemble_run(items, t_end, ts, 1, mode, traj_id_base=1000, max_events=W.max_events)
+        base = 1000
+        for i, it in enumerate(W.items):
+            ref = orc.simulate(it.model, mode, it.x0, t_end, ts, 1, n_traj=it.n_traj, traj_id_base=base,
+                               max_events=W.max_events, threads=ORACLE_THREADS)
+            assert_parity(ref, run.snapshots(i), run.stats(i), mode, it.model.name)
+            base += it.n_traj
+
+
+def test_full_size_schlogl_sampled(gpu, orc):
+    """The benchmark workload (100,000 trajectories, default launch) on a
+    sample of trajectory ids spread over the whole range."""
+    W = wl.config_schlogl()
+    it = W.items[0]
+    sample = np.unique(np.concatenate([np.arange(0, 100_000, 997), [99_999, 65_535, 65_536]]))
+    for mode in ("FP64", "MIX_F16_SR"):
+        run, snap, st = run_both(gpu, orc, it.model, it.x0, it.n_traj, W.t_end, W.snap_t, mode, seed=W.seed,
+                                 max_events=W.max_events, indices=sample)
+        assert np.all(run.stats(0)["status"] == 0)
