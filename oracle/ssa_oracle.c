@@ -182,10 +182,13 @@ float or_nlog32(float u)
 /*   bf16:  8 significand bits, min normal exponent -126, overflow at 2^128. */
 /* v is any double; the result is the rounded value (exact in float).        */
 /* rb < 0: round to nearest, ties to even.                                   */
-/* rb in [0, 65535]: stochastic rounding (Sec. 3.3): with x- <= |v| < x+ the */
-/* neighbours on the format's grid, the magnitude goes to x+ iff             */
-/* rb < floor(65536 * (|v| - x-) / (x+ - x-)); x+ beyond the largest finite  */
-/* value is infinity.                                                         */
+/* rb in [0, 65535]: stochastic rounding (Sec. 3.3). With x- <= |v| < x+ the */
+/* neighbours on the format's grid and f = (|v| - x-)/(x+ - x-), the         */
+/* magnitude goes to x+ when the top B bits of the halfword rb, read as an   */
+/* integer, plus floor(f * 2^B) reach 2^B; B = 16 for bf16 and 13 for fp16.  */
+/* For uniform rb this happens with probability floor(f 2^B)/2^B, i.e. the   */
+/* SR probability f to within 2^-B. x+ beyond the largest finite value is    */
+/* infinity.                                                                  */
 /* ------------------------------------------------------------------------- */
 enum { OR_FP64 = 0, OR_FP32 = 1, OR_FP16 = 2, OR_BF16 = 3 };
 
@@ -212,10 +215,14 @@ double or_round16(int fmt, double v, int rb)
     double fl = floor(q);
     double frac = q - fl;          /* exact */
     int up;
-    if (rb < 0)
+    if (rb < 0) {
         up = frac > 0.5 || (frac == 0.5 && fmod(fl, 2.0) == 1.0);
-    else
-        up = (double)rb < floor(frac * 65536.0);
+    } else {
+        int B = fmt == OR_FP16 ? 13 : 16;
+        double scale = ldexp(1.0, B);
+        double rtop = (double)(rb >> (16 - B));  /* top B bits of the halfword */
+        up = rtop + floor(frac * scale) >= scale;
+    }
     double r = (fl + (double)up) * ulp;
     if (r >= ovf)
         r = INFINITY;

@@ -176,8 +176,9 @@ def test_round16_rne_from_double_is_nearest_grid_point(orc, fmt):
 @pytest.mark.parametrize("fmt", [2, 3])
 def test_sr_neighbours_and_unbiased(orc, fmt):
     """SR (Sec. 3.3): every outcome is one of the two bracketing grid points, and
-    over all 2^16 halfwords the mean equals x to within ulp/2^16 (the halfword's
-    resolution); exact grid points never move."""
+    over all 2^16 halfwords the mean equals x to within a 2^-B fraction of the
+    grid step (B = 13 random bits for fp16, 16 for bf16); exact grid points
+    never move."""
     pytest.importorskip("torch")
     g = _grid(fmt)
     rng = np.random.default_rng(20 + fmt)
@@ -194,11 +195,14 @@ def test_sr_neighbours_and_unbiased(orc, fmt):
         if x == lo:
             assert np.all(out == lo)
             continue
+        B = 13 if fmt == 2 else 16
         mean = lo + (hi - lo) * np.count_nonzero(out == hi) / 65536.0
-        assert abs(mean - x) <= (hi - lo) / 65536.0 * (1 + 1e-12)
-        # probability of rounding up is (x - lo) / (hi - lo), quantised down to 2^-16
+        assert abs(mean - x) <= (hi - lo) / 2.0 ** B * (1 + 1e-12)
+        # probability of rounding up is (x - lo) / (hi - lo), quantised down to 2^-B
         p_up = np.count_nonzero(out == hi) / 65536.0
-        assert 0 <= (x - lo) / (hi - lo) - p_up < 2.0 ** -16
+        assert 0 <= (x - lo) / (hi - lo) - p_up < 2.0 ** -B
+        # the decision depends only on the top B bits of the halfword
+        np.testing.assert_array_equal(out.reshape(2 ** B, -1), np.repeat(out[:: 2 ** (16 - B), None], 2 ** (16 - B), 1))
 
 
 def test_sr_overflow_to_infinity(orc):
