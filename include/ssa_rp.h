@@ -213,6 +213,12 @@ const char *ssa_version(void);
  * Errors: as ssa_ensemble_run's validation; SSA_E_COMPILE. */
 int ssa_prepare(const ssa_run_desc *desc);
 
+/* Compile if needed and write to path (a buffer of len bytes) the file name
+ * of the cached code object ssa_ensemble_run would load for desc, for
+ * instruction-level analysis. Needs no GPU. Errors: validation codes;
+ * SSA_E_INVALID if the buffer is too small; SSA_E_COMPILE. */
+int ssa_kernel_file(const ssa_run_desc *desc, char *path, size_t len);
+
 /* Write the generated kernel source for desc to the file `path` (for
  * inspection). Errors: validation codes; SSA_E_INVALID if path cannot be
  * opened. */

@@ -286,7 +286,8 @@ struct CompiledKernel {
     std::vector<char> code;
 };
 
-int compile_source(const std::string &src, const std::string &arch, std::vector<char> &code)
+int compile_source(const std::string &src, const std::string &arch, std::vector<char> &code,
+                   std::string *path_out = nullptr)
 {
     const std::string key = arch + "\n" + src;
     uint64_t h = fnv1a(key);
@@ -296,6 +297,8 @@ int compile_source(const std::string &src, const std::string &arch, std::vector<
     std::snprintf(name, sizeof name, "%016llx.co", (unsigned long long)h);
     const std::string dir = cache_dir();
     const std::string path = dir + "/" + name;
+    if (path_out)
+        *path_out = path;
     {
         std::ifstream in(path, std::ios::binary);
         if (in) {
@@ -1005,6 +1008,26 @@ int ssa_prepare(const ssa_run_desc *desc)
     build_source(desc, src);
     std::vector<char> code;
     return compile_source(src, "gfx950", code);
+}
+
+// Compile (if needed) and report the on-disk code object of a descriptor.
+int ssa_kernel_file(const ssa_run_desc *desc, char *path, size_t len)
+{
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    if (!path || len == 0)
+        return fail(SSA_E_INVALID, "path buffer is NULL or empty");
+    std::string src, file;
+    build_source(desc, src);
+    std::vector<char> code;
+    rc = compile_source(src, "gfx950", code, &file);
+    if (rc != SSA_OK)
+        return rc;
+    if (file.size() + 1 > len)
+        return fail(SSA_E_INVALID, "path buffer too small");
+    std::memcpy(path, file.c_str(), file.size() + 1);
+    return SSA_OK;
 }
 
 // Write the generated kernel source for a descriptor to `path` (inspection).

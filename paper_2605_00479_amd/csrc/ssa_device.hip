@@ -133,12 +133,16 @@ __device__ __forceinline__ float neg_log32(float u)
 
 // --------------------------------------------------------------------------
 // Rounding a binary32 value to fp16 / bf16 (result carried as binary32).
-// Formats per Table tab:formats: fp16 has 11 significand bits and normals
-// from 2^-14; bf16 keeps binary32's exponent range with 8 significand bits.
-// RNE uses the hardware conversions (IEEE round-to-nearest-even with
-// subnormals kept, overflow to infinity). SR rounds the magnitude up iff the
-// halfword rb is below floor(2^16 * fraction of a grid step dropped).
+// Formats per Table tab:formats. Round-to-nearest-even uses the IEEE
+// conversions (subnormals kept, overflow to infinity). Stochastic rounding
+// uses gfx950's SR conversions: with f the dropped fraction of a grid step,
+// the magnitude rounds up when the top B bits of the 16-bit halfword plus
+// floor(f 2^B) reach 2^B (B = 16 for bf16, 13 for fp16); the instructions read
+// their random bits from the upper half of the operand, hence rb << 16.
 // --------------------------------------------------------------------------
+typedef __bf16 ssa_v2bf16 __attribute__((ext_vector_type(2)));
+typedef _Float16 ssa_v2f16 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float rne_f16(float v)
 {
     return (float)(_Float16)v;
@@ -146,38 +150,21 @@ __device__ __forceinline__ float rne_f16(float v)
 
 __device__ __forceinline__ float rne_bf16(float v)
 {
-    u32 b = __float_as_uint(v);
-    b = b + 0x7FFFu + ((b >> 16) & 1u);
-    return __uint_as_float(b & 0xFFFF0000u);
+    return (float)(__bf16)v;
 }
 
 __device__ __forceinline__ float sr_bf16(float v, u32 rb)
 {
-    u32 b = __float_as_uint(v);
-    u32 up = rb < (b & 0xFFFFu) ? 0x10000u : 0u;
-    return __uint_as_float((b & 0xFFFF0000u) + up);
+    ssa_v2bf16 z = {};
+    ssa_v2bf16 r = __builtin_amdgcn_cvt_sr_bf16_f32(z, v, rb << 16, false);
+    return (float)r[0];
 }
 
 __device__ __forceinline__ float sr_f16(float v, u32 rb)
 {
-    u32 b = __float_as_uint(v);
-    u32 mag = b & 0x7FFFFFFFu;
-    u32 sgn = b & 0x80000000u;
-    if (mag >= 0x47800000u)                    // |v| >= 2^16, inf or NaN
-        return mag > 0x7F800000u ? v : __uint_as_float(sgn | 0x7F800000u);
-    if (mag >= 0x38800000u) {                  // fp16 normal range, 13 bits dropped
-        u32 up = rb < ((mag & 0x1FFFu) << 3) ? 0x2000u : 0u;
-        u32 r = (mag & ~0x1FFFu) + up;
-        if (r >= 0x47800000u)
-            r = 0x7F800000u;
-        return __uint_as_float(sgn | r);
-    }
-    // fp16 subnormal range: grid step 2^-24
-    float q = __uint_as_float(mag) * 0x1p24f;
-    float fl = __builtin_floorf(q);
-    u32 thr = (u32)((q - fl) * 65536.0f);
-    float r = (fl + (rb < thr ? 1.0f : 0.0f)) * 0x1p-24f;
-    return __uint_as_float(sgn | __float_as_uint(r));
+    ssa_v2f16 z = {};
+    ssa_v2f16 r = __builtin_amdgcn_cvt_sr_f16_f32(z, v, rb << 16, false);
+    return (float)r[0];
 }
 
 // --------------------------------------------------------------------------
@@ -342,6 +329,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     Tm t = 0;
     u64 n = 0;
     i32 k = 0;
+    Tm t_next = 0;     // time of snapshot k (infinity past the last row of this launch)
     float mrun = 0.0f;
     u32 idx = 0;
     bool active = false;
@@ -399,6 +387,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                                 active = false;
                             }
                         }
+                        t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
                     }
                 }
                 if (base + cnt >= I.E)
@@ -470,57 +459,51 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 for (int j = 1; j < M; ++j)
                     S[j] = P::acc(S[j - 1], a[j], pool.hw(SLOT_SUM + j - 1));
                 const A a0 = S[M - 1];
-                if (!bad) {
-                    if (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f)))
-                        status = ST_OVERFLOW;
-                    else if (!(a0 > (A)0))
-                        status = ST_ABSORBED;
+                if (!bad)
+                    status = !(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
+                                 ? ST_OVERFLOW
+                                 : (!(a0 > (A)0) ? ST_ABSORBED : -1);
+                // ---- waiting time and clock (formed on every lane, used only if the event fires)
+                Tm t_new;
+                if constexpr (P::WIDE) {
+                    t_new = t + neg_log64(u1) / a0;
+                } else if constexpr (P::UNI) {
+                    A lg = P::arnd(neg_log32(u1), pool.hw(SLOT_LOG));
+                    A tau = P::arnd(lg / a0, pool.hw(SLOT_TAU));
+                    if constexpr (P::NORM)
+                        tau = P::arnd(tau / m, pool.hw(SLOT_TAUM));
+                    t_new = P::arnd(t + tau, pool.hw(SLOT_TIME));
+                } else {
+                    t_new = t + neg_log32(u1) / a0;
                 }
-                if (status < 0) {
-                    // ---- waiting time and clock
-                    Tm t_new;
-                    if constexpr (P::WIDE) {
-                        t_new = t + neg_log64(u1) / a0;
-                    } else if constexpr (P::UNI) {
-                        A lg = P::arnd(neg_log32(u1), pool.hw(SLOT_LOG));
-                        A tau = P::arnd(lg / a0, pool.hw(SLOT_TAU));
-                        if constexpr (P::NORM)
-                            tau = P::arnd(tau / m, pool.hw(SLOT_TAUM));
-                        t_new = P::arnd(t + tau, pool.hw(SLOT_TIME));
-                    } else {
-                        t_new = t + neg_log32(u1) / a0;
-                    }
-                    // ---- snapshots strictly before t_new hold the current state
-                    while (k < L.k_hi && snap_time<P>(L, k) < t_new) {
+                // ---- snapshots strictly before t_new hold the current state (rare)
+                if (status < 0 && t_next < t_new) {
+                    do {
 #pragma unroll
                         for (int s = 0; s < N; ++s)
                             I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
                         ++k;
-                    }
-                    if (t_new > t_end) {
-                        status = ST_DONE;
-                    } else if (!L.last && k >= L.k_hi) {
-                        status = ST_SUSPENDED;   // event n is redone by the next chunk
-                    } else {
-                        // ---- selection and integer update
-                        A target = P::arnd(u2 * a0, pool.hw(SLOT_TARGET));
-                        int mu = 0;
-#pragma unroll
-                        for (int j = 0; j < M; ++j)
-                            mu += (S[j] <= target) ? 1 : 0;
-                        if (mu == M) {
-                            mu = 0;
-#pragma unroll
-                            for (int j = 0; j < M; ++j)
-                                mu = (a[j] > (T)0) ? j : mu;
-                        }
-                        Md::update(x, mu);
-                        t = t_new;
-                        ++n;
-                        if (L.max_events && n == L.max_events)
-                            status = ST_CAPPED;
-                    }
+                        t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
+                    } while (t_next < t_new);
                 }
+                if (status < 0)
+                    status = t_new > t_end ? ST_DONE
+                                           : ((!L.last && k >= L.k_hi) ? ST_SUSPENDED : -1);
+                const bool fire = status < 0;
+                // ---- selection and integer update (mu = M means no reaction fires)
+                A target = P::arnd(u2 * a0, pool.hw(SLOT_TARGET));
+                int mu = 0, last_pos = 0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    mu += (S[j] <= target) ? 1 : 0;
+                    last_pos = (a[j] > (T)0) ? j : last_pos;
+                }
+                mu = mu == M ? last_pos : mu;
+                Md::update(x, fire ? mu : M);
+                t = fire ? t_new : t;
+                n += fire ? 1u : 0u;
+                if (fire && L.max_events && n == L.max_events)
+                    status = ST_CAPPED;
                 if (status >= 0) {
                     // ---- finish (or suspend) this trajectory
                     if (status != ST_SUSPENDED) {

@@ -1,0 +1,175 @@
+"""Count the VALU work of one event in a compiled ssa_kernel code object.
+
+The kernel's event loop is the innermost loop that contains the Philox
+multiplies (v_mad_u64_u32). Its every-event path is the set of blocks that
+(a) dominate the first Philox block from the loop header and (b) lie on every
+path from that block back to the loop latch. Rare paths (snapshot stores,
+trajectory completion, the selection fallback, refills) are excluded by
+construction. Each VALU instruction on the path is weighted by its issue cost
+in full-rate lane slots: 4 for the quarter-rate integer multiplies and
+transcendental ops, 1 otherwise.
+
+Usage: python -m paper_2605_00479_amd.csrc.valu_count <file.co>
+"""
+from __future__ import annotations
+
+import re
+import subprocess
+import sys
+
+OBJDUMP = "/opt/rocm/llvm/bin/llvm-objdump"
+
+QUARTER_RATE = re.compile(
+    r"^v_(mad_u64_u32|mad_i64_i32|mul_lo_u32|mul_hi_u32|mul_hi_i32|mul_lo_i32|rcp_|rsq_|sqrt_|log_|exp_|"
+    r"sin_|cos_|rcp_iflag)")
+
+_LINE = re.compile(r"^\s+(\S+)(.*?)//\s*([0-9A-Fa-f]+):.*?(?:<(\w+)\+0x([0-9a-f]+)>)?\s*$")
+
+
+def disassemble(co_path: str, func: str = "ssa_kernel"):
+    out = subprocess.run([OBJDUMP, "-d", "--no-show-raw-insn", co_path], capture_output=True, text=True,
+                         check=True).stdout
+    insts, cur, base = [], None, None
+    for line in out.splitlines():
+        m = re.match(r"^([0-9a-f]+) <(\w+)>:", line)
+        if m:
+            cur = m.group(2)
+            base = int(m.group(1), 16)
+            continue
+        if cur != func:
+            continue
+        m = _LINE.match(line)
+        if not m:
+            continue
+        op, addr = m.group(1), int(m.group(3), 16)
+        target = base + int(m.group(5), 16) if m.group(4) == func and m.group(5) else None
+        insts.append((addr, op, target))
+    return insts
+
+
+def build_cfg(insts):
+    leaders = {insts[0][0]}
+    for i, (addr, op, tgt) in enumerate(insts):
+        if op.startswith(("s_branch", "s_cbranch")):
+            if tgt is not None:
+                leaders.add(tgt)
+            if i + 1 < len(insts):
+                leaders.add(insts[i + 1][0])
+        if op == "s_endpgm" and i + 1 < len(insts):
+            leaders.add(insts[i + 1][0])
+    blocks, order = {}, []
+    cur = None
+    for addr, op, tgt in insts:
+        if addr in leaders:
+            cur = addr
+            blocks[cur] = []
+            order.append(cur)
+        blocks[cur].append((addr, op, tgt))
+    succ = {}
+    for i, b in enumerate(order):
+        last_op, last_tgt = blocks[b][-1][1], blocks[b][-1][2]
+        nxt = order[i + 1] if i + 1 < len(order) else None
+        s = []
+        if last_op.startswith("s_branch"):
+            s = [last_tgt]
+        elif last_op.startswith("s_cbranch"):
+            s = [last_tgt, nxt]
+        elif last_op == "s_endpgm":
+            s = []
+        else:
+            s = [nxt]
+        succ[b] = [x for x in s if x is not None]
+    return blocks, order, succ
+
+
+def dominators(nodes, succ, root):
+    pred = {n: [] for n in nodes}
+    for n in nodes:
+        for s in succ.get(n, []):
+            if s in pred:
+                pred[s].append(n)
+    dom = {n: set(nodes) for n in nodes}
+    dom[root] = {root}
+    changed = True
+    while changed:
+        changed = False
+        for n in nodes:
+            if n == root:
+                continue
+            ps = [dom[p] for p in pred[n]]
+            new = ({n} | set.intersection(*ps)) if ps else {n}
+            if new != dom[n]:
+                dom[n] = new
+                changed = True
+    return dom
+
+
+def reachable(succ, root, allowed):
+    seen, stack = {root}, [root]
+    while stack:
+        n = stack.pop()
+        for s in succ.get(n, []):
+            if s in allowed and s not in seen:
+                seen.add(s)
+                stack.append(s)
+    return seen
+
+
+def event_path(co_path: str):
+    insts = disassemble(co_path)
+    blocks, order, succ = build_cfg(insts)
+    nodes = set(order)
+    dom = dominators(order, succ, order[0])
+    # natural loops from back edges
+    loops = []
+    for u in order:
+        for v in succ[u]:
+            if v in dom[u]:
+                body = {v}
+                stack = [u]
+                while stack:
+                    n = stack.pop()
+                    if n not in body:
+                        body.add(n)
+                        stack.extend(p for p in order if n in succ[p])
+                loops.append((v, u, body))
+
+    def is_mul(op):   # the Philox 32x32->64 multiplies (fused, or split into high/low halves)
+        return op in ("v_mad_u64_u32", "v_mul_hi_u32")
+
+    def n_mad(bs):
+        return sum(1 for b in bs for _, op, _ in blocks[b] if is_mul(op))
+
+    cands = [lp for lp in loops if n_mad(lp[2]) >= 18]
+    header, latch, body = min(cands, key=lambda lp: len(lp[2]))
+    first_mad = min((b for b in body if any(is_mul(op) for _, op, _ in blocks[b])))
+    # (a) blocks dominating the Philox entry from the header, inside the loop
+    sub = sorted(reachable(succ, header, body))
+    d_h = dominators(sub, {n: [s for s in succ[n] if s in body and s != header] for n in sub}, header)
+    pre = d_h[first_mad]
+    # (b) blocks on every path from the Philox entry to the latch
+    region = sorted(reachable({n: [s for s in succ[n] if s != header] for n in body}, first_mad, body))
+    d_e = dominators(region, {n: [s for s in succ[n] if s in region and s != header] for n in region}, first_mad)
+    path = pre | d_e[latch]
+    return blocks, sorted(path)
+
+
+def count(co_path: str) -> dict:
+    blocks, path = event_path(co_path)
+    n_valu = n_slots = n_salu = 0
+    quarter = 0
+    for b in path:
+        for _, op, _ in blocks[b]:
+            if op.startswith("v_"):
+                w = 4 if QUARTER_RATE.match(op) else 1
+                n_valu += 1
+                n_slots += w
+                quarter += w == 4
+            elif op.startswith("s_"):
+                n_salu += 1
+    return {"valu_insts": n_valu, "valu_slots": n_slots, "quarter_rate_insts": quarter, "salu_insts": n_salu,
+            "blocks": len(path)}
+
+
+if __name__ == "__main__":
+    print(count(sys.argv[1]))

@@ -57,7 +57,7 @@ class ssa_run_info(ctypes.Structure):
 
 EXPORTS = ("ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
            "ssa_snapshots_get", "ssa_run_stats_get", "ssa_run_info_get", "ssa_run_destroy",
-           "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source")
+           "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source", "ssa_kernel_file")
 
 _lib = None
 
@@ -84,9 +84,7 @@ def lib():
         L.ssa_version.restype = ctypes.c_char_p
         L.ssa_prepare.argtypes = [ctypes.POINTER(ssa_run_desc)]
         L.ssa_dump_source.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p]
-        for name in EXPORTS:
-            if getattr(L, name).restype is ctypes.c_int:
-                pass
+        L.ssa_kernel_file.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p, ctypes.c_size_t]
         _lib = L
     return _lib
 
@@ -256,6 +254,14 @@ def ssa_prepare(items, t_end, snap_t, mode, **kw):
     """Compile and cache the kernel for a run description (no GPU needed)."""
     d, keep = _desc(items, t_end, snap_t, 0, mode, **kw)
     _check(lib().ssa_prepare(ctypes.byref(d)))
+
+
+def ssa_kernel_file(items, t_end, snap_t, mode, **kw) -> str:
+    """Path of the cached code object a run description uses (compiles if needed)."""
+    d, keep = _desc(items, t_end, snap_t, 0, mode, **kw)
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().ssa_kernel_file(ctypes.byref(d), buf, len(buf)))
+    return buf.value.decode()
 
 
 def ssa_dump_source(items, t_end, snap_t, mode, path, **kw):

@@ -105,6 +105,14 @@ def test_self_repressor_activation_and_repression(gpu, orc):
         run_both(gpu, orc, spec, np.array([3, 0], np.int32), 700, 20.0, wl.snapshot_grid(20.0, 9), mode, seed=9)
 
 
+@pytest.mark.parametrize("mode", ["MIX_F16_SR", "MIX_F16_RTN", "MIX_BF16_SR"])
+def test_fp16_subnormal_propensities(gpu, orc, mode):
+    """Rates around 1e-6 put every propensity in fp16's subnormal range, where
+    stochastic rounding decides on fewer dropped-fraction bits."""
+    m = wl.birth_death(3e-6, 2e-6)
+    run_both(gpu, orc, m, np.array([3], np.int32), 3000, 4e5, [1e5, 2e5, 4e5], mode, seed=12)
+
+
 def test_refill_path_single_workgroup(gpu, orc):
     """One workgroup of one wave runs 2,000 trajectories: every lane refills
     many times from the work counter."""
