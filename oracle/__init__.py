@@ -87,22 +87,24 @@ def _load():
 class Mode:
     fmt: int
     uniform: bool = False
-    sr: bool = False
+    sr: int = 0          # 0 round to nearest, 1 SR at every op, 2 SR at accumulation points
     norm: bool = False
 
 
 def parse_mode(name: str) -> Mode:
-    """Parse FP64 / FP32 / {MIX,UNI}_{F16,BF16}_{RTN,SR}[_NORM]."""
+    """Parse FP64 / FP32 / {MIX,UNI}_{F16,BF16}_{RTN,SR}[_NORM] / UNI_{F16,BF16}_SRA[_NORM]
+    (SRA: stochastic rounding only at the partial sums and the clock)."""
     if name == "FP64":
         return Mode(FMT_FP64)
     if name == "FP32":
         return Mode(FMT_FP32)
     parts = name.split("_")
     if len(parts) not in (3, 4) or parts[0] not in ("MIX", "UNI") or parts[1] not in ("F16", "BF16") \
-            or parts[2] not in ("RTN", "SR") or (len(parts) == 4 and (parts[3] != "NORM" or parts[0] != "UNI")):
+            or parts[2] not in ("RTN", "SR", "SRA") or (len(parts) == 4 and (parts[3] != "NORM" or parts[0] != "UNI")) \
+            or (parts[2] == "SRA" and parts[0] != "UNI"):
         raise ValueError(f"unknown precision mode {name!r}")
-    return Mode(FMT_FP16 if parts[1] == "F16" else FMT_BF16, parts[0] == "UNI", parts[2] == "SR",
-                len(parts) == 4)
+    return Mode(FMT_FP16 if parts[1] == "F16" else FMT_BF16, parts[0] == "UNI",
+                {"RTN": 0, "SR": 1, "SRA": 2}[parts[2]], len(parts) == 4)
 
 
 def _ptr(a):

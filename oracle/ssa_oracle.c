@@ -251,7 +251,9 @@ typedef struct {
 typedef struct {
     int32_t fmt;     /* OR_FP64, OR_FP32, OR_FP16, OR_BF16 */
     int32_t uniform; /* 16-bit formats: 0 = mixed, 1 = uniform */
-    int32_t sr;      /* 16-bit formats: 1 = stochastic rounding */
+    int32_t sr;      /* 16-bit formats: 0 = round to nearest, 1 = stochastic rounding
+                        at every op, 2 = stochastic rounding only where values
+                        accumulate (partial sums and the clock; uniform mode) */
     int32_t norm;    /* uniform 16-bit: running-max normalisation */
 } or_mode;
 
@@ -526,6 +528,9 @@ static void traj_fp32(const or_model *md, const or_run *run, int64_t idx, const 
 /*   propensities: reaction by reaction, op by op  [0, P)                     */
 /*   uniform mode, in order: M normalisations (if norm), M-1 partial sums,    */
 /*     -ln(u1), tau, tau/m (if norm), t + tau, u2 * a0.                      */
+/* With SR only at accumulation points (the paper's "selective SR", Sec. 3.3  */
+/* last paragraph) the partial sums take slots 0..M-2 and the clock update    */
+/* slot M-1; every other op rounds to nearest and takes no slot.              */
 /* Halfword of slot s: slots 0..3 are words 2,3 of the event's stream-0 draw  */
 /* (low half first); slot 4 + 8q + r is half r%2 of word r/2 of the stream    */
 /* q+1 draw.                                                                  */
@@ -574,6 +579,7 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
     const int N = md->n_species, M = md->n_reactions, K = run->n_snap;
     const uint32_t id = run->traj_id_base + (uint32_t)idx;
     const int uni = mode.uniform, norm = mode.uniform && mode.norm;
+    const int selective = mode.sr == 2;
     int32_t x[MAXN];
     float c[MAXM], hb[MAXM], hK[MAXM];
     int base[MAXM];
@@ -592,11 +598,11 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
     }
     /* accumulation-phase slots (uniform mode) */
     const int slot_norm = P;
-    const int slot_sum = P + (norm ? M : 0);     /* S_j uses slot_sum + j - 1 */
+    const int slot_sum = selective ? 0 : P + (norm ? M : 0);  /* S_j uses slot_sum + j - 1 */
     const int slot_log = slot_sum + (M - 1);
     const int slot_tau = slot_log + 1;
     const int slot_taum = slot_tau + 1;           /* norm only */
-    const int slot_time = slot_tau + 1 + (norm ? 1 : 0);
+    const int slot_time = selective ? M - 1 : slot_tau + 1 + (norm ? 1 : 0);
     const int slot_target = slot_time + 1;
 
     const float t_end = (float)run->t_end;
@@ -605,7 +611,8 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
     uint64_t n = 0;
     int k = 0, status;
     sr_ctx ctx;
-    rounder R = {mode.fmt, mode.sr, &ctx};
+    rounder R = {mode.fmt, mode.sr == 1, &ctx};    /* propensity and other ops */
+    rounder RA = {mode.fmt, mode.sr >= 1, &ctx};   /* partial sums and the clock */
     for (;;) {
         ctx.seed = run->seed;
         ctx.id = id;
@@ -668,7 +675,7 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
         }
         S[0] = a[0];
         for (int j = 1; j < M; ++j)
-            S[j] = uni ? rnd(&R, S[j - 1] + a[j], slot_sum + j - 1) : S[j - 1] + a[j];
+            S[j] = uni ? rnd(&RA, S[j - 1] + a[j], slot_sum + j - 1) : S[j - 1] + a[j];
         float a0 = S[M - 1];
         if (!(a0 <= 3.40282347e38f)) { status = ST_OVERFLOW; break; }
         if (!(a0 > 0.0f)) { status = ST_ABSORBED; break; }
@@ -679,7 +686,7 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
             tau = rnd(&R, L / a0, slot_tau);
             if (norm)
                 tau = rnd(&R, tau / m, slot_taum);
-            t_new = rnd(&R, t + tau, slot_time);
+            t_new = rnd(&RA, t + tau, slot_time);
         } else {
             tau = L / a0;
             t_new = t + tau;
@@ -720,7 +727,9 @@ int or_simulate(const or_model *md, or_mode mode, const or_run *run, const int64
     if (md->n_species < 1 || md->n_species > MAXN || md->n_reactions < 1 ||
         md->n_reactions > MAXM || run->n_snap < 0)
         return -1;
-    if (mode.fmt < OR_FP64 || mode.fmt > OR_BF16)
+    if (mode.fmt < OR_FP64 || mode.fmt > OR_BF16 || mode.sr < 0 || mode.sr > 2)
+        return -1;
+    if (mode.sr == 2 && !mode.uniform)
         return -1;
     if (run->set_rate && run->traj_per_set < 1)
         return -1;

@@ -228,7 +228,7 @@ def closed_dimer_law(total=100, kf=1e-3, kr=0.1):
 
 @pytest.mark.parametrize("mode", ["FP64", "FP32", "MIX_F16_RTN", "MIX_F16_SR", "MIX_BF16_SR",
                                   "UNI_F16_RTN", "UNI_F16_SR", "UNI_BF16_RTN", "UNI_BF16_SR",
-                                  "UNI_BF16_SR_NORM"])
+                                  "UNI_BF16_SR_NORM", "UNI_F16_SRA", "UNI_BF16_SRA_NORM"])
 def test_closed_dimer_conservation_every_mode(orc, mode):
     m = wl.dimer_closed()
     r = run(orc, m, mode, [100, 0], 20.0, np.arange(21.0), 2000, seed=8, max_events=200_000)
@@ -375,3 +375,20 @@ def test_uniform_sr_is_unbiased_where_rtn_stagnates(orc):
     rtn = run(orc, m, "UNI_BF16_RTN", [0], 30.0, [30.0], 20_000, seed=18, max_events=100_000)["snap"][0, 0]
     assert abs(sr.mean() - ref.mean()) < 4 * math.sqrt(40.0 / 20_000)
     assert ref.mean() - rtn.mean() > 6 * math.sqrt(2 * 20.0 / 20_000)
+    # SR at the accumulation points alone also removes the clock's stagnation bias
+    sra = run(orc, m, "UNI_BF16_SRA", [0], 30.0, [30.0], 20_000, seed=19)["snap"][0, 0]
+    assert abs(sra.mean() - ref.mean()) < 0.25 * (ref.mean() - rtn.mean())
+
+
+def test_selective_sr_draws_only_for_sums_and_clock(orc):
+    """With SR at accumulation points only, propensities round to nearest: on a
+    network whose uniform-mode ops are all exact except the clock and sums,
+    selective SR and full SR see the same propensities; and a mixed-mode
+    request for it is rejected (mixed mode accumulates in binary32)."""
+    with pytest.raises(ValueError):
+        orc.parse_mode("MIX_F16_SRA")
+    m = wl.birth_death(16.0, 0.125)
+    a = run(orc, m, "UNI_F16_SRA", [0], 5.0, [5.0], 500, seed=20)
+    b = run(orc, m, "UNI_F16_SRA", [0], 5.0, [5.0], 500, seed=20, threads=1)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
