@@ -64,22 +64,37 @@ class _Run(ctypes.Structure):
 _lib = None
 
 
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile oracle source text (e.g. a deliberately altered copy used by the
+    tests that check the pins catch mistakes) into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
+                    "-fPIC", "-w", "-o", out_path, src, "-lm"], check=True)
+    return out_path
+
+
+def _open(path):
+    lib = ctypes.CDLL(path)
+    lib.or_simulate.restype = ctypes.c_int
+    lib.or_simulate.argtypes = [ctypes.POINTER(_Model), _Mode, ctypes.POINTER(_Run),
+                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    for name in ("or_philox_batch", "or_nlog64_batch", "or_nlog32_batch", "or_uniform_batch"):
+        getattr(lib, name).restype = None
+    lib.or_round16_batch.restype = None
+    lib.or_round16_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int64]
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        lib.or_simulate.restype = ctypes.c_int
-        lib.or_simulate.argtypes = [ctypes.POINTER(_Model), _Mode, ctypes.POINTER(_Run),
-                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
-        for name in ("or_philox_batch", "or_nlog64_batch", "or_nlog32_batch", "or_uniform_batch"):
-            getattr(lib, name).restype = None
-        lib.or_round16_batch.restype = None
-        lib.or_round16_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
-                                         ctypes.c_void_p, ctypes.c_int64]
-        _lib = lib
+        _lib = _open(_LIB)
     return _lib
 
 
@@ -113,13 +128,14 @@ def _ptr(a):
 
 def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: int | None = None,
              indices=None, traj_id_base: int = 0, max_events: int = 0, set_rate=None,
-             traj_per_set: int = 0, threads: int = 1):
+             traj_per_set: int = 0, threads: int = 1, lib=None):
     """Run trajectories ``indices`` (default ``range(n_traj)``) of an ensemble.
 
     Returns a dict with ``snap`` [K, N, count] int32, ``n_events`` uint64,
-    ``t_last`` float64 and ``status`` uint8 per trajectory.
+    ``t_last`` float64 and ``status`` uint8 per trajectory. ``lib``: a library
+    from ``_open`` (default: the built oracle).
     """
-    lib = _load()
+    lib = lib or _load()
     if indices is None:
         indices = np.arange(int(n_traj), dtype=np.int64)
     idx = np.ascontiguousarray(indices, dtype=np.int64)
@@ -159,9 +175,9 @@ def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: i
     return {"snap": snap, "n_events": n_ev, "t_last": t_last, "status": status}
 
 
-def philox(ctr, key):
+def philox(ctr, key, lib=None):
     """Philox4x32-10 of counters ctr [n,4] under keys key [n,2] -> [n,4] uint32."""
-    lib = _load()
+    lib = lib or _load()
     c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
     k = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
     out = np.empty_like(c)
@@ -170,27 +186,27 @@ def philox(ctr, key):
     return out
 
 
-def nlog64(u):
+def nlog64(u, lib=None):
     """-ln(u), FP64 project logarithm, for u in (0, 1]."""
-    lib = _load()
+    lib = lib or _load()
     a = np.ascontiguousarray(u, dtype=np.float64)
     out = np.empty_like(a)
     lib.or_nlog64_batch(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(out.ctypes.data), ctypes.c_int64(a.size))
     return out
 
 
-def nlog32(u):
+def nlog32(u, lib=None):
     """-ln(u), FP32 project logarithm, for u in (0, 1]."""
-    lib = _load()
+    lib = lib or _load()
     a = np.ascontiguousarray(u, dtype=np.float32)
     out = np.empty_like(a)
     lib.or_nlog32_batch(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(out.ctypes.data), ctypes.c_int64(a.size))
     return out
 
 
-def round16(fmt: int, v, rb=None):
+def round16(fmt: int, v, rb=None, lib=None):
     """Round doubles to fp16 (fmt=2) or bf16 (fmt=3): RNE, or SR with halfwords rb."""
-    lib = _load()
+    lib = lib or _load()
     a = np.ascontiguousarray(v, dtype=np.float64)
     r = None if rb is None else np.ascontiguousarray(np.broadcast_to(rb, a.shape), dtype=np.int32)
     out = np.empty_like(a)
@@ -199,9 +215,9 @@ def round16(fmt: int, v, rb=None):
     return out
 
 
-def uniforms(w):
+def uniforms(w, lib=None):
     """(u53 from word pairs, u24 from the first word of each pair) for w [n,2]."""
-    lib = _load()
+    lib = lib or _load()
     a = np.ascontiguousarray(w, dtype=np.uint32).reshape(-1, 2)
     u53 = np.empty(a.shape[0], dtype=np.float64)
     u24 = np.empty(a.shape[0], dtype=np.float32)

@@ -1,0 +1,204 @@
+"""The pins have teeth: plant one plausible mistake at a time in a copy of the
+oracle source (CPU only), rebuild it, and check that a pin of the kind used
+in test_oracle_numerics.py / test_oracle_laws.py rejects the altered oracle.
+
+Mistakes a pin cannot see by construction are listed at the end with the
+reason (ties that occur with probability ~2^-53)."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2605_00479_amd import workloads as wl
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "ssa_oracle.c")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(v, 16) for v in line.split()])
+    return np.array(rows, dtype=np.uint64).astype(np.uint32)
+
+
+# ------------------------------------------------------------------ detectors (each returns True if the pin fails)
+def kat_fails(lib):
+    kat = _kat()
+    return not np.array_equal(oracle.philox(kat[:, :4], kat[:, 4:6], lib=lib), kat[:, 6:])
+
+
+def uniform_range_fails(lib):
+    w = np.array([[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [12345, 678]], np.uint32)
+    u53, u24 = oracle.uniforms(w, lib=lib)
+    return not (np.all(u53 > 0) and np.all(u53 <= 1) and np.all(u24 > 0) and np.all(u24 <= 1))
+
+
+def log_ulp_fails(lib):
+    import mpmath
+    mpmath.mp.prec = 120
+    rng = np.random.default_rng(5)
+    u = (rng.integers(0, 2**53, 3000, dtype=np.uint64).astype(np.float64) + 1.0) * 2.0 ** -53
+    got = oracle.nlog64(u, lib=lib)
+    worst = max(abs(float(mpmath.mpf(g) + mpmath.log(mpmath.mpf(float(v))))) / float(np.spacing(abs(g)) or 1e-300)
+                for v, g in zip(u, got))
+    return worst > 2.0
+
+
+def rne_fails(lib):
+    rng = np.random.default_rng(9)
+    v = np.concatenate([np.arange(0, 4096, 0.5), rng.uniform(0, 70000, 20000)])
+    return not np.array_equal(oracle.round16(2, v, lib=lib), v.astype(np.float16).astype(np.float64))
+
+
+def sr_probability_fails(lib):
+    rng = np.random.default_rng(21)
+    xs = np.exp(rng.uniform(np.log(1e-3), np.log(6e4), 60)).astype(np.float32).astype(np.float64)
+    rb = np.arange(65536, dtype=np.int32)
+    for x in xs:
+        out = oracle.round16(2, np.full(65536, x), rb, lib=lib)
+        lo, hi = out.min(), out.max()
+        if lo == hi:
+            continue
+        p_up = np.count_nonzero(out == hi) / 65536.0
+        if not (0 <= (x - lo) / (hi - lo) - p_up < 2.0 ** -13):
+            return True
+    return False
+
+
+def chi2_p(sample, pmf):
+    if np.any(sample < 0):          # counts are non-negative in every valid path
+        return 0.0
+    counts = np.bincount(sample, minlength=pmf.size)[: pmf.size].astype(float)
+    counts[-1] += np.count_nonzero(sample >= pmf.size)
+    keep = pmf * sample.size >= 10
+    obs = np.append(counts[keep], counts[~keep].sum())
+    exp = np.append(pmf[keep] * sample.size, pmf[~keep].sum() * sample.size)
+    if exp[-1] < 1e-9:
+        obs, exp = obs[:-1], exp[:-1]
+    exp *= obs.sum() / exp.sum()
+    return stats.chisquare(obs, exp).pvalue
+
+
+def birth_death_law_fails(lib):
+    """Poisson law at T and the expected number of events, as in the birth-death pin."""
+    r = oracle.simulate(wl.birth_death(), "FP64", [0], 100.0, [100.0], 1, n_traj=6000, threads=8, lib=lib)
+    lam = 100 * (1 - math.exp(-10))
+    if chi2_p(r["snap"][0, 0], stats.poisson.pmf(np.arange(200), lam)) < 1e-3:
+        return True
+    e_events = 10 * 100 + 0.1 * (lam / (1 - math.exp(-10.0))) * (100 - (1 - math.exp(-10.0)) / 0.1)
+    ne = r["n_events"].astype(float)
+    return abs(ne.mean() - e_events) > 5 * ne.std() / math.sqrt(ne.size)
+
+
+def closed_dimer_law_fails(lib):
+    dmax = 50
+    logp = np.zeros(dmax + 1)
+    for d in range(dmax):
+        A = 100 - 2 * d
+        logp[d + 1] = logp[d] + math.log(1e-3 * A * (A - 1) / 2) - math.log(0.1 * (d + 1))
+    p = np.exp(logp - logp.max())
+    p /= p.sum()
+    r = oracle.simulate(wl.dimer_closed(), "FP64", [100, 0], 100.0, [100.0], 9, n_traj=20000, threads=8, lib=lib)
+    return chi2_p(r["snap"][0, 1], p) < 1e-3
+
+
+def hill_law_fails(lib):
+    b, v, K, h, d = 2.0, 30.0, 10.0, 2, 1.0
+    r = oracle.simulate(wl.self_repressor(b, v, K, h, d), "FP64", [0], 30.0, [30.0], 11, n_traj=20000,
+                        threads=8, lib=lib)
+    logp = np.zeros(120)
+    for n in range(119):
+        logp[n + 1] = logp[n] + math.log(b + v / (1 + (n / K) ** h)) - math.log(d * (n + 1))
+    p = np.exp(logp - logp.max())
+    p /= p.sum()
+    return chi2_p(r["snap"][0, 0], p) < 1e-3
+
+
+def mixed_equals_fp32_fails(lib):
+    m = wl.birth_death(16.0, 0.125)
+    ts = wl.snapshot_grid(40.0, 41)
+    a = oracle.simulate(m, "FP32", [0], 40.0, ts, 16, n_traj=1000, threads=8, lib=lib)
+    for mode in ("MIX_F16_RTN", "MIX_BF16_RTN", "MIX_BF16_SR"):
+        b = oracle.simulate(m, mode, [0], 40.0, ts, 16, n_traj=1000, threads=8, lib=lib)
+        if not all(np.array_equal(a[k], b[k]) for k in a):
+            return True
+    return False
+
+
+def uniform_stagnation_fails(lib):
+    m = wl.birth_death(20.0, 1.0)
+    ref = oracle.simulate(m, "FP64", [0], 30.0, [30.0], 17, n_traj=20000, threads=8, lib=lib)["snap"][0, 0]
+    rtn = oracle.simulate(m, "UNI_BF16_RTN", [0], 30.0, [30.0], 18, n_traj=20000, max_events=100000, threads=8,
+                          lib=lib)["snap"][0, 0]
+    return not (ref.mean() - rtn.mean() > 6 * math.sqrt(2 * 20.0 / 20000))
+
+
+def transient_snapshots_fail(lib):
+    ts = np.array([0.0, 0.05, 0.3, 1.0, 2.5])
+    r = oracle.simulate(wl.birth_death(5.0, 1.0), "FP64", [0], 2.5, ts, 3, n_traj=20000, threads=8, lib=lib)
+    for k, t in enumerate(ts[1:], start=1):
+        lam = 5.0 * (1 - math.exp(-t))
+        if chi2_p(r["snap"][k, 0], stats.poisson.pmf(np.arange(40), lam)) < 1e-3:
+            return True
+    return not np.all(r["snap"][0, 0] == 0)
+
+
+MUTATIONS = [
+    ("philox key not advanced", "            k0 += PHILOX_WEYL0;\n            k1 += PHILOX_WEYL1;\n", "", kat_fails),
+    ("philox low halves swapped", "        uint32_t n1 = lo1;", "        uint32_t n1 = lo0;", kat_fails),
+    ("uniform can be zero", "    return (double)(m + 1u) * 0x1p-53;", "    return (double)(m) * 0x1p-53;",
+     uniform_range_fails),
+    ("log series sign", "    double lnf = s2 + s2 * p;", "    double lnf = s2 - s2 * p;", log_ulp_fails),
+    ("log drops low part of ln2", "    double r = ed * LN2_HI_D + (ed * LN2_LO_D + lnf);",
+     "    double r = ed * LN2_HI_D + lnf;", log_ulp_fails),
+    ("RNE ties away from zero", "(frac == 0.5 && fmod(fl, 2.0) == 1.0)", "(frac == 0.5)", rne_fails),
+    ("SR strict comparison", "        up = rtop + floor(frac * scale) >= scale;",
+     "        up = rtop + floor(frac * scale) > scale;", sr_probability_fails),
+    ("mass action without 1/o!", "    return k / (double)d;", "    return k;", closed_dimer_law_fails),
+    ("falling factorial offset dropped", "                        acc = acc * (double)(x[s] - i);",
+     "                        acc = acc * (double)(x[s]);", closed_dimer_law_fails),
+    ("net change of the wrong reaction", "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[mu * N + s];\n        t = t_new;\n        ++n;\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    *n_out = n;\n    *t_out = t;",
+     "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[((mu + 1) % M) * N + s];\n        t = t_new;\n        ++n;\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    *n_out = n;\n    *t_out = t;",
+     birth_death_law_fails),
+    ("waiting time with a wrong rate", "        double tau = or_nlog64(u1) / a0;", "        double tau = or_nlog64(u1) / (a0 + a[0]);",
+     birth_death_law_fails),
+    ("first partial sum skips a_0", "        S[0] = a[0];\n        for (int j = 1; j < M; ++j)\n            S[j] = S[j - 1] + a[j];\n        double a0",
+     "        S[0] = 0.0;\n        for (int j = 1; j < M; ++j)\n            S[j] = S[j - 1] + a[j];\n        double a0", birth_death_law_fails),
+    ("Hill power one too high", "                for (int i = 1; i < md->hill_h[j]; ++i)\n                    qh = qh * q;\n                double d = 1.0 + qh;",
+     "                for (int i = 0; i < md->hill_h[j]; ++i)\n                    qh = qh * q;\n                double d = 1.0 + qh;", hill_law_fails),
+    ("snapshot written after the event", "        while (k < K && run->snap_t[k] < t_new) {\n            write_snap(o, k, N, x);\n            ++k;\n        }\n        if (t_new > run->t_end) { status = ST_DONE; break; }\n        double target",
+     "        if (t_new > run->t_end) { status = ST_DONE; while (k < K && run->snap_t[k] < t_new) { write_snap(o, k, N, x); ++k; } break; }\n        double target",
+     transient_snapshots_fail),
+    ("mixed mode rounds the sums", "            S[j] = uni ? rnd(&RA, S[j - 1] + a[j], slot_sum + j - 1) : S[j - 1] + a[j];",
+     "            S[j] = rnd(&RA, S[j - 1] + a[j], slot_sum + j - 1);", mixed_equals_fp32_fails),
+    ("uniform clock kept in binary32", "            t_new = rnd(&RA, t + tau, slot_time);", "            t_new = t + tau;",
+     uniform_stagnation_fails),
+]
+
+
+@pytest.mark.parametrize("name,find,repl,detect", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_detects_planted_mistake(tmp_path, name, find, repl, detect):
+    src = open(SRC).read()
+    assert src.count(find) == 1, f"mutation anchor not unique for {name!r}"
+    path = oracle.build_variant(src.replace(find, repl), str(tmp_path / "variant.so"))
+    lib = oracle._open(path)
+    assert detect(lib), f"the pin did not catch: {name}"
+
+
+@pytest.mark.parametrize("detect", [kat_fails, uniform_range_fails, rne_fails, sr_probability_fails,
+                                    birth_death_law_fails, closed_dimer_law_fails, hill_law_fails,
+                                    mixed_equals_fp32_fails, uniform_stagnation_fails, transient_snapshots_fail])
+def test_detectors_accept_the_unaltered_oracle(tmp_path, detect):
+    path = oracle.build_variant(open(SRC).read(), str(tmp_path / "same.so"))
+    assert not detect(oracle._open(path))
+
+
+# Not detectable by a pin: the tie rules (S_j > target vs >=, snapshot t_k < t_new vs <=)
+# differ only when two binary64 values coincide exactly, probability about 2^-53 per
+# event; the GPU parity tests compare them with the kernel over ~10^9 events instead.
