@@ -1,8 +1,9 @@
-"""Benchmark: SSA events/s on one MI355X for the Schloegl ensemble
-(100,000 trajectories, T_end = 10, 101 snapshots), mixed FP16 with
-stochastic rounding (the reported value) against the FP64 direct method.
+"""Benchmark: SSA events/s on one MI355X, mixed FP16 with stochastic rounding
+(the reported value) against the FP64 direct method, on the Schloegl ensemble
+(100,000 trajectories, T_end = 10, 101 snapshots) unless --config names
+another configured workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config schlogl]
 
 A step is one complete ensemble run (every trajectory from t = 0 to T_end:
 RNG draws, propensities, sums, waiting times, snapshot stores, selection and
@@ -23,59 +24,120 @@ sys.path.insert(0, ROOT)
 
 PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: full-rate VALU lane slots/s
 
+# species whose end-time marginal the fidelity statistics use, per network
+MARGINALS = {"birth_death": (0,), "schlogl": (0,), "telegraph": (2,), "dimer_open": (0, 1),
+             "repressilator": (3,), "dimer_closed": (0, 1)}
+
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--config", default="schlogl")
+    p.add_argument("--n-traj", type=int, default=0, help="override the ensemble size (0: the config's)")
     p.add_argument("--mode", default="MIX_F16_SR")
     p.add_argument("--ref-mode", default="FP64")
-    p.add_argument("--n-traj", type=int, default=100_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fidelity", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4000, help="trajectories the oracle runs for cpu_baseline")
-    p.add_argument("--verbose", action="store_true")
+    p.add_argument("--chunks", type=int, default=0, help="0: autotuned (or 1 without --no-autotune's tuning)")
+    p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--valu-peak", action="store_true", help="also measure per-class VALU rates")
+    p.add_argument("--block", type=int, default=0)
+    p.add_argument("--grid", type=int, default=0)
     return p.parse_args()
 
 
-def timed_runs(ssa, items, W, mode, steps, warmup, log):
+def make_workload(name, n):
+    from paper_2605_00479_amd import workloads as wl
+    make = wl.CONFIGS[name]
+    if not n:
+        return make()
+    if name == "dimer_sweep":
+        return make(n_sets=max(1, n // 256))
+    if name == "heterogeneous":
+        return make(n_traj_total=n)
+    return make(n)
+
+
+def launch(ssa, items, W, mode, seed, args):
+    return ssa.ssa_ensemble_run(items, W.t_end, W.snap_t, seed, mode, max_events=W.max_events,
+                                n_chunks=args.chunks, block_size=args.block, grid_size=args.grid)
+
+
+def marginals(run, W):
+    out = {}
+    for i, it in enumerate(W.items):
+        snap = run.snapshots(i)
+        for s in MARGINALS.get(it.model.name, (0,)):
+            out[f"{it.model.name}:{it.model.species[s]}"] = snap[-1, s].copy() if snap.shape[0] else np.zeros(0)
+    return out
+
+
+def timed_runs(ssa, items, W, mode, args, log):
     import torch
-    for _ in range(warmup):
-        r = ssa.ssa_ensemble_run(items, W.t_end, W.snap_t, W.seed, mode, max_events=W.max_events)
-        r.wait()
-        del r
+    if not args.no_autotune and not (args.block or args.grid or args.chunks):
+        tuned = ssa.ssa_autotune(items, W.t_end, W.snap_t, W.seed, mode, max_events=W.max_events)
+        log(f"[bench] autotune {mode}: {tuned}")
+    for _ in range(args.warmup):
+        launch(ssa, items, W, mode, W.seed, args).wait()
     torch.cuda.synchronize()
     runs = []
     t0 = time.perf_counter()
-    for _ in range(steps):
-        runs.append(ssa.ssa_ensemble_run(items, W.t_end, W.snap_t, W.seed, mode, max_events=W.max_events))
+    for _ in range(args.steps):
+        runs.append(launch(ssa, items, W, mode, W.seed, args))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     infos = [r.info() for r in runs]
     events = sum(i["total_events"] for i in infos)
     kern_ms = [i["kernel_ms"] for i in infos]
-    log(f"[bench] {mode}: {steps} steps, {events} events, wall {wall:.3f}s, kernel ms {kern_ms}")
+    log(f"[bench] {mode}: {args.steps} steps, {events} events, wall {wall:.3f}s, kernel ms {kern_ms}")
     last = runs[-1]
-    x_end = last.snapshots(0)[-1, 0].copy()
-    st = last.stats(0)
-    return {"wall_s": wall, "events": events, "events_per_step": events / steps,
-            "kernel_ms_avg": float(np.mean(kern_ms)), "info": infos[-1], "x_end": x_end,
-            "status_counts": np.bincount(st["status"], minlength=4).tolist()}
+    status = np.zeros(4, dtype=np.int64)
+    for i in range(len(W.items)):
+        status += np.bincount(last.stats(i)["status"], minlength=4)[:4]
+    return {"wall_s": wall, "events": events, "events_per_step": events / args.steps,
+            "kernel_ms_avg": float(np.mean(kern_ms)), "info": infos[-1],
+            "marg": None if args.no_fidelity else marginals(last, W), "status_counts": status.tolist()}
+
+
+VALU_CLASSES = [("v_fma_f64", 1), ("v_fmamk_f32", 1), ("v_pk_fma_f16", 1), ("v_mad_u64_u32 + v_xor_b32", 5),
+                ("v_bitop3_b32", 1), ("v_cvt_sr_f16_f32 + v_cvt_f32_f16 + v_add_f32", 3), ("v_rcp_f32 + v_add_f32", 5)]
+
+
+def valu_peak(log):
+    """Measured chain-step rates per instruction class; 'slots' is the weight the
+    roofline assumes for one step (quarter-rate ops = 4)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_00479_amd", "libssa_valu_peak.so"))
+    lib.valu_peak_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    out = []
+    for op, (name, slots) in enumerate(VALU_CLASSES):
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        if lib.valu_peak_run(op, 4096, ctypes.byref(rate), ctypes.byref(ms)) != 0:
+            raise RuntimeError("valu_peak_run failed")
+        out.append({"class": name, "steps_per_s": rate.value, "assumed_slots": slots,
+                    "implied_slots_per_s": rate.value * slots, "ms": ms.value})
+        log(f"[bench] valu {name}: {rate.value:.3e} steps/s x {slots} slots = {rate.value * slots:.3e}")
+    return out
 
 
 def cpu_baseline(W, mode, n_sample, log):
     import oracle
     threads = min(16, os.cpu_count() or 1)
     it = W.items[0]
-    idx = np.arange(n_sample, dtype=np.int64)
+    n = min(n_sample, it.n_traj)
+    idx = np.arange(n, dtype=np.int64)
     t0 = time.perf_counter()
-    r = oracle.simulate(it.model, mode, it.x0, W.t_end, W.snap_t, W.seed, indices=idx,
-                        max_events=W.max_events, threads=threads)
+    r = oracle.simulate(it.model, mode, it.x0, W.t_end, W.snap_t, W.seed, indices=idx, max_events=W.max_events,
+                        set_rate=it.set_rate, traj_per_set=it.traj_per_set, threads=threads)
     dt = time.perf_counter() - t0
     ev = int(r["n_events"].sum())
-    log(f"[bench] cpu oracle {mode}: {n_sample} trajectories, {ev} events in {dt:.2f}s on {threads} threads")
+    log(f"[bench] cpu oracle {mode}: {n} trajectories, {ev} events in {dt:.2f}s on {threads} threads")
     return {"value": ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"trajectories 0..{n_sample - 1} of the same Schloegl ensemble, {mode}, full horizon"}
+            "sample": f"trajectories 0..{n - 1} of the same {it.model.name} ensemble, {mode}, full horizon"}
 
 
 def main():
@@ -86,40 +148,47 @@ def main():
               file=sys.stderr)
         return 2
     import torch
-    from paper_2605_00479_amd import ssa, stats, workloads as wl
+    from paper_2605_00479_amd import ssa, stats
     from paper_2605_00479_amd.csrc import valu_count
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     ssa.lib()
-    W = wl.config_schlogl(args.n_traj)
+    W = make_workload(args.config, args.n_traj)
     items = ssa.items_from_workload(W)
-    log(f"[bench] workload schlogl: {W.n_traj} trajectories, T_end {W.t_end}, {len(W.snap_t)} snapshots")
+    log(f"[bench] workload {W.name}: {W.n_traj} trajectories, T_end {W.t_end}, {len(W.snap_t)} snapshots")
 
-    main_res = timed_runs(ssa, items, W, args.mode, args.steps, args.warmup, log)
-    ref_res = timed_runs(ssa, items, W, args.ref_mode, args.steps, args.warmup, log)
+    main_res = timed_runs(ssa, items, W, args.mode, args, log)
+    ref_res = timed_runs(ssa, items, W, args.ref_mode, args, log)
 
-    # fidelity of the end-time ensemble (species X at T_end) against FP64:
-    # independent seeds for the acceptance test, common random numbers as the paper's comparison
-    W_ind = wl.config_schlogl(args.n_traj)
-    W_ind.seed = W.seed + 1000
-    ind = ssa.ssa_ensemble_run(items, W_ind.t_end, W_ind.snap_t, W_ind.seed, args.mode, max_events=W.max_events)
-    x_ind = ind.snapshots(0)[-1, 0]
-    fid_ind = stats.compare(ref_res["x_end"], x_ind)
-    fid_crn = stats.compare(ref_res["x_end"], main_res["x_end"])
+    fidelity = None
+    if not args.no_fidelity:
+        # end-time marginals against FP64: independent seeds (acceptance) and common random numbers
+        ind = launch(ssa, items, W, args.mode, W.seed + 1000, args)
+        m_ind = marginals(ind, W)
+        fidelity = {}
+        for key, ref in ref_res["marg"].items():
+            fidelity[key] = {"independent_seeds": stats.compare(ref, m_ind[key]),
+                             "common_random_numbers": stats.compare(ref, main_res["marg"][key])}
+        fidelity["ks_pass_all"] = bool(all(v["independent_seeds"]["ks_p"] > 0.05
+                                           for k, v in fidelity.items() if k != "ks_pass_all"))
 
-    # roofline: VALU slots of one event (every-event path of this kernel's code object)
+    # roofline: VALU slots of one event on the every-event path of the launched code object
     def per_event(mode):
         f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode)
         return valu_count.count(f)
 
-    ve = per_event(args.mode)
-    ve_ref = per_event(args.ref_mode)
+    ve, ve_ref = per_event(args.mode), per_event(args.ref_mode)
     ms = main_res["kernel_ms_avg"]
     achieved = main_res["events_per_step"] * ve["valu_slots"] / (ms * 1e-3)
     value = main_res["events"] / main_res["wall_s"]
     ref_value = ref_res["events"] / ref_res["wall_s"]
-
+    desc = {"schlogl": "schlogl bistable, X0=250, T_end=10, 101 snapshots",
+            "birth_death": "birth-death kb=10 kd=0.1, X0=0, T_end=100, snapshot at 100",
+            "telegraph": "telegraph k_on=0.05 k_off=0.1 k_m=20, gene off, T_end=200, 201 snapshots",
+            "dimer_sweep": "open dimer, log-uniform parameter sets (seed 7) x 256, T_end=50, 51 snapshots",
+            "heterogeneous": "five networks in one launch, T_end=500, 501 snapshots"}[W.name]
+    out_cfg_chunks = main_res["info"]["n_launches"]
     out = {
         "metric": "SSA events/s/GPU: FP16-SR mixed vs FP64 direct, at KS p>0.05 vs oracle",
         "value": value,
@@ -133,24 +202,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f16(SR)+f32" if args.mode == "MIX_F16_SR" else args.mode,
         "data": "synthetic",
-        "config": {"workload": f"schlogl bistable, {W.n_traj} trajectories, X0=250, T_end=10, 101 snapshots, "
-                               f"seed {W.seed}", "mode": args.mode, "ref_mode": args.ref_mode,
-                   "events_per_step": main_res["events_per_step"]},
+        "config": {"workload": f"{desc}, {W.n_traj} trajectories, seed {W.seed}", "mode": args.mode,
+                   "ref_mode": args.ref_mode, "events_per_step": main_res["events_per_step"],
+                   "n_chunks": out_cfg_chunks},
         "fp64": {"value": ref_value, "unit": "events/s", "ms_per_step": ref_res["wall_s"] / args.steps * 1e3,
                  "kernel_ms": ref_res["kernel_ms_avg"], "events_per_step": ref_res["events_per_step"],
                  "valu_slots_per_event": ve_ref["valu_slots"],
                  "valu_frac": ref_res["events_per_step"] * ve_ref["valu_slots"] / (ref_res["kernel_ms_avg"] * 1e-3)
                  / PEAK_VALU_SLOTS},
         "speedup_vs_fp64": value / ref_value,
-        "fidelity": {"independent_seeds": fid_ind, "common_random_numbers": fid_crn,
-                     "ks_pass": bool(fid_ind["ks_p"] > 0.05)},
+        "fidelity": fidelity,
         "status_counts": main_res["status_counts"],
         "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
+        "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
                      "kernel": "ssa_kernel", "kernel_ms": ms, "valu_slots_per_event": ve["valu_slots"],
                      "valu_insts_per_event": ve["valu_insts"]},
     }
+    if args.valu_peak:
+        out["valu_peak"] = valu_peak(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.mode, args.cpu_sample, log)
     print(json.dumps(out))

@@ -58,6 +58,9 @@ extern "C" {
 #define SSA_ACC_UNIFORM 1  /* every operation in the 16-bit format          */
 #define SSA_RND_RTN 0      /* round to nearest, ties to even                */
 #define SSA_RND_SR 1       /* stochastic rounding with Philox halfwords     */
+#define SSA_RND_SR_ACC 2   /* SR only at the partial sums and the clock,
+                              round to nearest elsewhere (uniform mode; the
+                              selective SR of Sec. 3.3, last paragraph)     */
 #define SSA_NORM_NONE 0
 #define SSA_NORM_RUNNING_MAX 1 /* uniform 16-bit only */
 
@@ -132,14 +135,21 @@ typedef struct ssa_item {
  *     that split an ensemble differently give identical trajectories.
  *   format/accum/rounding/norm: SSA_FMT_*, SSA_ACC_*, SSA_RND_*, SSA_NORM_*.
  *     FP64 and FP32 take accum = MIXED, rounding = RTN, norm = NONE.
- *     norm = RUNNING_MAX needs a 16-bit format and accum = UNIFORM.
+ *     norm = RUNNING_MAX and rounding = SR_ACC need a 16-bit format and
+ *     accum = UNIFORM.
  *   max_events: per-trajectory event cap (0 = none).
  *   hip_stream: hipStream_t to run on (NULL = the null stream).
- *   n_chunks: 0 or 1 runs the horizon in one launch; c > 1 splits the
- *     snapshot rows into c windows, one launch each, replayed from a captured
- *     hipGraph; results are bit-identical to one launch.
- *   block_size, grid_size: launch shape (0 = library choice); block_size a
- *     multiple of 64 up to 1024. */
+ *   n_chunks: 1 runs the horizon in one launch; c > 1 splits the snapshot
+ *     rows into c windows, one launch each, replayed from a captured hipGraph;
+ *     results are bit-identical to one launch. 0 = the autotuned choice for
+ *     this kernel and workload shape if ssa_autotune stored one, else 1.
+ *   block_size, grid_size: launch shape; 0 = the autotuned choice if stored,
+ *     else 256 threads and enough workgroups for one trajectory per lane (up
+ *     to what stays resident). block_size a multiple of 64 up to 256.
+ *   reorder: chunked runs only. 0 or 1: before each chunk after the first,
+ *     trajectories are claimed in order of the events they fired in the
+ *     previous chunk, heaviest first (results are unchanged: draws are keyed
+ *     by trajectory id); -1: claim in id order. */
 typedef struct ssa_run_desc {
     const ssa_item *items;
     int32_t n_items;
@@ -157,6 +167,8 @@ typedef struct ssa_run_desc {
     void *hip_stream;
     int32_t block_size;
     int32_t grid_size;
+    int32_t reorder;
+    int32_t reserved;
 } ssa_run_desc;
 
 /* Start an ensemble run; returns once the work is queued on hip_stream
@@ -196,6 +208,26 @@ typedef struct ssa_run_info {
 
 /* Fill info for a run (waits for it). */
 int ssa_run_info_get(const ssa_run *run, ssa_run_info *info);
+
+/* Result of ssa_autotune. */
+typedef struct ssa_tune_result {
+    int32_t block_size;   /* threads per workgroup */
+    int32_t grid_size;    /* workgroups: sets waves per CU and trajectories per lane */
+    int32_t n_chunks;     /* snapshot windows (hipGraph-replayed launches) */
+    int32_t n_candidates; /* launch shapes timed */
+    double best_ms;       /* device time of the chosen shape */
+} ssa_tune_result;
+
+/* Launch-shape autotuner. Runs desc's workload (into scratch outputs owned by
+ * the library; desc's output pointers are ignored) once per candidate shape:
+ * block size 64 or 256; grid holding 1, 2 or 4 waves per SIMD with lane
+ * refill, or one lane per trajectory; one launch or 4 snapshot chunks. Times
+ * each with HIP events, keeps the fastest in memory and in
+ * <cache dir>/tune.txt, keyed by the generated kernel and the workload shape
+ * (ensemble sizes, snapshot count, t_end, max_events). Later runs of the same
+ * key that pass block_size = 0, grid_size = 0 or n_chunks = 0 use it.
+ * res may be NULL. Errors: as ssa_ensemble_run. */
+int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res);
 
 /* Release a run and the device memory it owns (NULL is ignored). */
 void ssa_run_destroy(ssa_run *run);

@@ -17,6 +17,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libssa_rp.so")
+PEAK_LIB = os.path.join(PKG, "libssa_valu_peak.so")
 
 HIP_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -49,6 +50,13 @@ def build_library(verbose: bool = False) -> str:
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
     os.replace(LIB + ".tmp", LIB)
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", *HIP_FLAGS,
+           os.path.join(HERE, "valu_peak.hip"), "-o", PEAK_LIB + ".tmp"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building libssa_valu_peak.so failed")
+    os.replace(PEAK_LIB + ".tmp", PEAK_LIB)
     return LIB
 
 

@@ -221,7 +221,7 @@ struct ModeSpec {
         if (fmt == SSA_FMT_FP32)
             return "PrecF32";
         std::string f = fmt == SSA_FMT_FP16 ? "FMT_FP16" : "FMT_BF16";
-        return "Prec16<" + f + ", " + (rnd == SSA_RND_SR ? "true" : "false") + ", " +
+        return "Prec16<" + f + ", " + std::to_string(rnd) + ", " +
                (accum == SSA_ACC_UNIFORM ? "true" : "false") + ", " +
                (norm == SSA_NORM_RUNNING_MAX ? "true" : "false") + ">";
     }
@@ -346,6 +346,7 @@ struct Loaded {
     hipModule_t mod = nullptr;
     hipFunction_t kernel = nullptr;
     hipFunction_t fill = nullptr;
+    hipFunction_t rg_hist = nullptr, rg_scan = nullptr, rg_scatter = nullptr;
     int vgprs = -1;
 };
 
@@ -372,12 +373,70 @@ int get_kernel(const std::string &src, Loaded &out)
     HIP_TRY(hipModuleLoadData(&ld.mod, code.data()));
     HIP_TRY(hipModuleGetFunction(&ld.kernel, ld.mod, "ssa_kernel"));
     HIP_TRY(hipModuleGetFunction(&ld.fill, ld.mod, "ssa_fill_u32"));
+    HIP_TRY(hipModuleGetFunction(&ld.rg_hist, ld.mod, "ssa_regroup_hist"));
+    HIP_TRY(hipModuleGetFunction(&ld.rg_scan, ld.mod, "ssa_regroup_scan"));
+    HIP_TRY(hipModuleGetFunction(&ld.rg_scatter, ld.mod, "ssa_regroup_scatter"));
     int regs = -1;
     if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, ld.kernel) == hipSuccess)
         ld.vgprs = regs;
     g_loaded[key] = ld;
     out = ld;
     return SSA_OK;
+}
+
+// ------------------------------------------------------------------ tuning cache
+// Launch shapes chosen by ssa_autotune, keyed by the kernel source and the
+// workload's shape, kept in memory and appended to <cache dir>/tune.txt.
+struct Tuned {
+    int block = 0, grid = 0, chunks = 0;
+    double ms = 0.0;
+};
+
+std::mutex g_tune_mu;
+std::unordered_map<std::string, Tuned> g_tuned;
+bool g_tune_loaded = false;
+
+std::string tune_key(const ssa_run_desc *d, const std::string &src)
+{
+    std::ostringstream k;
+    k << std::hex << fnv1a(src) << std::dec << ":" << d->n_snap << ":" << d->t_end << ":" << d->max_events;
+    for (int i = 0; i < d->n_items; ++i)
+        k << ":" << d->items[i].n_traj;
+    return k.str();
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded)
+        return;
+    g_tune_loaded = true;
+    std::ifstream in(cache_dir() + "/tune.txt");
+    std::string key;
+    Tuned t;
+    while (in >> key >> t.block >> t.grid >> t.chunks >> t.ms)
+        g_tuned[key] = t;
+}
+
+bool tune_lookup(const std::string &key, Tuned &t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tuned.find(key);
+    if (it == g_tuned.end())
+        return false;
+    t = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const Tuned &t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tuned[key] = t;
+    ::mkdir(cache_dir().c_str(), 0755);
+    std::ofstream out(cache_dir() + "/tune.txt", std::ios::app);
+    if (out)
+        out << key << " " << t.block << " " << t.grid << " " << t.chunks << " " << t.ms << "\n";
 }
 
 // ------------------------------------------------------------------ launch arguments
@@ -396,6 +455,8 @@ struct ItemArgsH {
     int32_t *ck;
     float *cm;
     uint32_t *counter;
+    const uint32_t *order;
+    uint32_t *work;
     uint32_t E;
     uint32_t traj_per_set;
     uint32_t id_base;
@@ -429,13 +490,16 @@ int validate_mode(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "format must be one of SSA_FMT_*");
     if (d->accum != SSA_ACC_MIXED && d->accum != SSA_ACC_UNIFORM)
         return fail(SSA_E_INVALID, "accum must be SSA_ACC_MIXED or SSA_ACC_UNIFORM");
-    if (d->rounding != SSA_RND_RTN && d->rounding != SSA_RND_SR)
-        return fail(SSA_E_INVALID, "rounding must be SSA_RND_RTN or SSA_RND_SR");
+    if (d->rounding != SSA_RND_RTN && d->rounding != SSA_RND_SR && d->rounding != SSA_RND_SR_ACC)
+        return fail(SSA_E_INVALID, "rounding must be SSA_RND_RTN, SSA_RND_SR or SSA_RND_SR_ACC");
     if (d->norm != SSA_NORM_NONE && d->norm != SSA_NORM_RUNNING_MAX)
         return fail(SSA_E_INVALID, "norm must be SSA_NORM_NONE or SSA_NORM_RUNNING_MAX");
     if (d->format <= SSA_FMT_FP32 &&
         (d->accum != SSA_ACC_MIXED || d->rounding != SSA_RND_RTN || d->norm != SSA_NORM_NONE))
         return fail(SSA_E_INVALID, "FP64/FP32 take accum=MIXED, rounding=RTN, norm=NONE");
+    if (d->rounding == SSA_RND_SR_ACC && d->accum != SSA_ACC_UNIFORM)
+        return fail(SSA_E_UNSUPPORTED, "SR at accumulation points is defined for uniform 16-bit mode only "
+                                       "(mixed mode accumulates in binary32)");
     if (d->norm == SSA_NORM_RUNNING_MAX && d->accum != SSA_ACC_UNIFORM)
         return fail(SSA_E_UNSUPPORTED, "propensity normalisation is defined for uniform 16-bit mode only");
     return SSA_OK;
@@ -469,6 +533,8 @@ int validate_desc(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
     if (d->grid_size < 0)
         return fail(SSA_E_INVALID, "grid_size must be >= 0");
+    if (d->reorder < -1 || d->reorder > 1)
+        return fail(SSA_E_INVALID, "reorder must be -1, 0 or 1");
     uint64_t total = 0;
     for (int i = 0; i < d->n_items; ++i) {
         const ssa_item &it = d->items[i];
@@ -530,6 +596,9 @@ struct ItemBuf {
     void *rates = nullptr;
     void *hill = nullptr;
     int32_t *x0 = nullptr;
+    uint32_t *order = nullptr;   // claim order for the next chunk (chunked runs)
+    uint32_t *work = nullptr;    // events per trajectory in the last chunk
+    uint32_t *hist = nullptr;    // 256 work classes
     uint32_t traj_per_set = 0;
     uint32_t id_base = 0;
 };
@@ -616,6 +685,8 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
             ia.ck = b.ck;
             ia.cm = b.cm;
             ia.counter = r->counters + (size_t)c * nI + i;
+            ia.order = (c > 0 && b.order) ? b.order : nullptr;
+            ia.work = b.work;
             ia.E = (uint32_t)b.E;
             ia.traj_per_set = b.traj_per_set;
             ia.id_base = b.id_base;
@@ -626,6 +697,24 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
         HIP_TRY(hipModuleLaunchKernel(ld.kernel, r->grid, 1, 1, r->block, 1, 1, 0, s, args, nullptr));
         if (!r->graph)
             HIP_TRY(hipEventRecord(r->kev[2 * c + 1], s));
+        // claim order for the next chunk: heaviest trajectories of this chunk first
+        if (c + 1 < n_chunks) {
+            for (int i = 0; i < nI; ++i) {
+                ItemBuf &b = r->items[i];
+                if (!b.order || b.E == 0)
+                    continue;
+                uint32_t nb = 256, zero = 0, E = (uint32_t)b.E;
+                uint32_t blocks = (uint32_t)std::min<int64_t>((b.E + 255) / 256, 1024);
+                void *fa[] = {&b.hist, &nb, &zero};
+                HIP_TRY(hipModuleLaunchKernel(ld.fill, 1, 1, 1, 256, 1, 1, 0, s, fa, nullptr));
+                void *ha[] = {&b.work, &E, &b.hist};
+                HIP_TRY(hipModuleLaunchKernel(ld.rg_hist, blocks, 1, 1, 256, 1, 1, 0, s, ha, nullptr));
+                void *sa[] = {&b.hist};
+                HIP_TRY(hipModuleLaunchKernel(ld.rg_scan, 1, 1, 1, 256, 1, 1, 0, s, sa, nullptr));
+                void *xa[] = {&b.work, &E, &b.hist, &b.order};
+                HIP_TRY(hipModuleLaunchKernel(ld.rg_scatter, blocks, 1, 1, 256, 1, 1, 0, s, xa, nullptr));
+            }
+        }
     }
     return SSA_OK;
 }
@@ -657,8 +746,14 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         return rc;
     r->vgprs = ld.vgprs;
 
+    // launch shape chosen by ssa_autotune for this kernel and workload, if any
+    Tuned tuned;
+    const bool have_tuned = (d->block_size == 0 || d->grid_size == 0 || d->n_chunks == 0) &&
+                            tune_lookup(tune_key(d, src), tuned);
     const bool wide = d->format == SSA_FMT_FP64;
-    int n_chunks = d->n_chunks <= 1 ? 1 : d->n_chunks;
+    int n_chunks = d->n_chunks == 0 ? (have_tuned ? tuned.chunks : 1) : d->n_chunks;
+    if (n_chunks < 1)
+        n_chunks = 1;
     if (n_chunks > std::max(r->K, 1))
         n_chunks = std::max(r->K, 1);
 
@@ -745,6 +840,9 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
             if ((rc = dalloc(r, &b.cx, (size_t)md.N * E)) || (rc = dalloc(r, &b.ct, E)) ||
                 (rc = dalloc(r, &b.cn, E)) || (rc = dalloc(r, &b.ck, E)) || (rc = dalloc(r, &b.cm, E)))
                 return rc;
+            if (d->reorder >= 0 && E > 0 &&
+                ((rc = dalloc(r, &b.order, E)) || (rc = dalloc(r, &b.work, E)) || (rc = dalloc(r, &b.hist, 256))))
+                return rc;
         }
         r->items.push_back(b);
     }
@@ -752,14 +850,16 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     // launch shape: enough waves to cover the ensemble, at most what stays resident
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
-    r->block = d->block_size ? d->block_size : 256;
+    r->block = d->block_size ? d->block_size : (have_tuned ? tuned.block : 256);
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel, r->block, 0));
     if (per_cu < 1)
         per_cu = 1;
     int64_t need = (total + r->block - 1) / r->block;
     int64_t resident = (int64_t)per_cu * cus;
-    int64_t grid = d->grid_size ? d->grid_size : std::max<int64_t>(1, std::min(need, resident));
+    int64_t grid = d->grid_size ? d->grid_size
+                                : (have_tuned && tuned.block == r->block ? tuned.grid
+                                                                          : std::max<int64_t>(1, std::min(need, resident)));
     r->grid = (int)grid;
 
     HIP_TRY(hipEventCreate(&r->ev0));
@@ -996,6 +1096,103 @@ void ssa_run_destroy(ssa_run *run) { release(run); }
 const char *ssa_last_error(void) { return g_err.c_str(); }
 
 const char *ssa_version(void) { return "ssa_rp 0.1 (gfx950)"; }
+
+// Time candidate launch shapes on the workload itself and remember the best.
+int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
+{
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    std::string src;
+    build_source(desc, src);
+    Loaded ld;
+    if ((rc = get_kernel(src, ld)) != SSA_OK)
+        return rc;
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t total = 0;
+    for (int i = 0; i < desc->n_items; ++i)
+        total += desc->items[i].n_traj;
+    struct Cand {
+        int block, grid, chunks;
+    };
+    std::vector<Cand> cands;
+    const int chunk_opts[] = {1, desc->n_snap >= 8 ? 4 : 1};
+    for (int block : {64, 256}) {
+        int per_cu = 0;
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel, block, 0));
+        per_cu = std::max(per_cu, 1);
+        const int64_t need = std::max<int64_t>(1, (total + block - 1) / block);
+        const int64_t resident = (int64_t)per_cu * cus;
+        const int waves_per_block = block / 64;
+        // waves per SIMD: 1, 2, 4, and enough lanes for one trajectory each
+        std::vector<int64_t> grids = {std::min(need, resident)};
+        for (int wps : {1, 2, 4}) {
+            int64_t g = (int64_t)cus * 4 * wps / waves_per_block;
+            if (g < need && g <= resident)
+                grids.push_back(g);
+        }
+        std::sort(grids.begin(), grids.end());
+        grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
+        for (int64_t g : grids)
+            for (int ch : chunk_opts)
+                cands.push_back({block, (int)g, ch});
+    }
+    cands.erase(std::unique(cands.begin(), cands.end(),
+                            [](const Cand &a, const Cand &b) {
+                                return a.block == b.block && a.grid == b.grid && a.chunks == b.chunks;
+                            }),
+                cands.end());
+    Tuned best;
+    best.ms = 1e300;
+    for (const Cand &c : cands) {
+        ssa_run_desc d2 = *desc;
+        std::vector<ssa_item> items(desc->items, desc->items + desc->n_items);
+        for (auto &it : items) {
+            it.d_snap = nullptr;
+            it.d_n_events = nullptr;
+            it.d_t_last = nullptr;
+            it.d_status = nullptr;
+        }
+        d2.items = items.data();
+        d2.block_size = c.block;
+        d2.grid_size = c.grid;
+        d2.n_chunks = c.chunks;
+        ssa_run *r = new (std::nothrow) ssa_run;
+        if (!r)
+            return fail(SSA_E_NOMEM, "out of host memory");
+        rc = run_impl(&d2, r);
+        float ms = 0.0f;
+        if (rc == SSA_OK) {
+            hipError_t e = hipEventSynchronize(r->ev1);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, r->ev0, r->ev1);
+            if (e != hipSuccess)
+                rc = fail(SSA_E_DEVICE, std::string("autotune trial: ") + hipGetErrorString(e));
+        }
+        std::string keep = g_err;
+        release(r);
+        g_err = keep;
+        if (rc != SSA_OK)
+            return rc;
+        if (ms < best.ms) {
+            best.block = c.block;
+            best.grid = c.grid;
+            best.chunks = c.chunks;
+            best.ms = ms;
+        }
+    }
+    tune_store(tune_key(desc, src), best);
+    if (res) {
+        res->block_size = best.block;
+        res->grid_size = best.grid;
+        res->n_chunks = best.chunks;
+        res->best_ms = best.ms;
+        res->n_candidates = (int32_t)cands.size();
+    }
+    return SSA_OK;
+}
 
 // Compile (and cache on disk) the kernel a run with this descriptor would use,
 // without touching a GPU. Used by the build step to fill the kernel cache.

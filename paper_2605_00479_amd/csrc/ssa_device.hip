@@ -40,14 +40,19 @@ struct W4 {
     u32 w0, w1, w2, w3;
 };
 
+__device__ __forceinline__ u32 xor3(u32 a, u32 b, u32 c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);   // a ^ b ^ c in one VALU op
+}
+
 __device__ __forceinline__ W4 philox10(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         u64 p0 = (u64)0xD2511F53u * (u64)c0;
         u64 p1 = (u64)0xCD9E8D57u * (u64)c2;
-        u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0;
-        u32 n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        u32 n0 = xor3((u32)(p1 >> 32), c1, k0);
+        u32 n2 = xor3((u32)(p0 >> 32), c3, k1);
         c1 = (u32)p1;
         c3 = (u32)p0;
         c0 = n0;
@@ -177,26 +182,28 @@ struct PrecF64 {
     typedef double T;
     typedef double A;
     typedef double Tm;
-    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true, SELECTIVE = false;
     __device__ static T cvt(i32 v, u32) { return (double)v; }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
     __device__ static T add(T a, T b, u32) { return a + b; }
     __device__ static A acc(A s, T a, u32) { return s + (A)a; }
     __device__ static A arnd(A v, u32) { return v; }
+    __device__ static A tacc(A v, u32) { return v; }
 };
 
 struct PrecF32 {
     typedef float T;
     typedef float A;
     typedef float Tm;
-    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false, SELECTIVE = false;
     __device__ static T cvt(i32 v, u32) { return (float)v; }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
     __device__ static T add(T a, T b, u32) { return a + b; }
     __device__ static A acc(A s, T a, u32) { return s + a; }
     __device__ static A arnd(A v, u32) { return v; }
+    __device__ static A tacc(A v, u32) { return v; }
 };
 
 template <int FMT, bool SRM>
@@ -208,18 +215,24 @@ __device__ __forceinline__ float rnd16(float v, u32 rb)
         return SRM ? sr_bf16(v, rb) : rne_bf16(v);
 }
 
-template <int FMT, bool SRM, bool UNIF, bool NRM>
+// RND: 0 round to nearest; 1 stochastic rounding after every 16-bit op;
+// 2 stochastic rounding only where values accumulate (partial sums and the
+// clock, uniform mode), round to nearest elsewhere - the selective SR the
+// paper names as untested (Sec. 3.3, last paragraph).
+template <int FMT, int RND, bool UNIF, bool NRM>
 struct Prec16 {
     typedef float T;
     typedef float A;
     typedef float Tm;
-    static constexpr bool SR = SRM, UNI = UNIF, NORM = NRM, WIDE = false;
-    __device__ static T cvt(i32 v, u32 rb) { return rnd16<FMT, SRM>((float)v, rb); }
-    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a * b, rb); }
-    __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a / b, rb); }
-    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SRM>(a + b, rb); }
-    __device__ static A acc(A s, T a, u32 rb) { return UNIF ? rnd16<FMT, SRM>(s + a, rb) : s + a; }
-    __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SRM>(v, rb) : v; }
+    static constexpr bool SR = RND != 0, UNI = UNIF, NORM = NRM, WIDE = false, SELECTIVE = RND == 2;
+    static constexpr bool SR_OPS = RND == 1, SR_ACC = RND != 0;
+    __device__ static T cvt(i32 v, u32 rb) { return rnd16<FMT, SR_OPS>((float)v, rb); }
+    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a * b, rb); }
+    __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a / b, rb); }
+    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a + b, rb); }
+    __device__ static A acc(A s, T a, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(s + a, rb) : s + a; }
+    __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_OPS>(v, rb) : v; }
+    __device__ static A tacc(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(v, rb) : v; }
 };
 
 // --------------------------------------------------------------------------
@@ -241,6 +254,46 @@ struct Pool {
 };
 
 // --------------------------------------------------------------------------
+// Everything an event takes from its random numbers alone: the rounding
+// halfword pool, -ln(u1) (rounded once in uniform mode) and u2. It depends on
+// (seed, trajectory, event index) only, so the kernel forms event n+1's draw
+// while event n's state-dependent chain runs.
+// --------------------------------------------------------------------------
+template <class P, int NSLOT>
+struct Draw {
+    Pool<NSLOT> pool;
+    typename P::A L;
+    typename P::A u2;
+};
+
+template <class P, int NSLOT, int SLOT_LOG>
+__device__ __forceinline__ Draw<P, NSLOT> make_draw(u64 n, u32 id, u32 k0, u32 k1)
+{
+    Draw<P, NSLOT> d;
+    W4 r0 = philox10((u32)n, (u32)(n >> 32), id, 0u, k0, k1);
+    if constexpr (NSLOT > 0) {
+        d.pool.w[0] = r0.w2;
+        d.pool.w[1] = r0.w3;
+#pragma unroll
+        for (int q = 1; q < Pool<NSLOT>::NSTREAM; ++q) {
+            W4 rq = philox10((u32)n, (u32)(n >> 32), id, (u32)q, k0, k1);
+            d.pool.w[2 + 4 * (q - 1) + 0] = rq.w0;
+            d.pool.w[2 + 4 * (q - 1) + 1] = rq.w1;
+            d.pool.w[2 + 4 * (q - 1) + 2] = rq.w2;
+            d.pool.w[2 + 4 * (q - 1) + 3] = rq.w3;
+        }
+    }
+    if constexpr (P::WIDE) {
+        d.L = neg_log64(unif53(r0.w0, r0.w1));
+        d.u2 = unif53(r0.w2, r0.w3);
+    } else {
+        d.L = P::arnd(neg_log32(unif24(r0.w0)), d.pool.hw(SLOT_LOG));
+        d.u2 = unif24(r0.w1);
+    }
+    return d;
+}
+
+// --------------------------------------------------------------------------
 // Launch arguments.
 // --------------------------------------------------------------------------
 struct ItemArgs {
@@ -257,6 +310,8 @@ struct ItemArgs {
     i32 *ck;                 // carry next snapshot index [E]
     float *cm;               // carry running maximum [E]
     u32 *counter;            // work counter of this item (starts at 0)
+    const u32 *order;        // claim order: trajectory of the w-th claim (NULL: w itself)
+    u32 *work;               // events each trajectory fired in this launch (NULL: not recorded)
     u32 E;                   // trajectories
     u32 traj_per_set;        // trajectories per rate set (0: one set)
     u32 id_base;             // Philox trajectory id of trajectory 0
@@ -310,13 +365,15 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     typedef typename P::A A;
     typedef typename P::Tm Tm;
     constexpr int N = Md::N, M = Md::M;
-    constexpr int NSLOT = P::SR ? (Md::NPROP + (P::UNI ? (P::NORM ? 2 * M + 4 : M + 3) : 0)) : 0;
+    // rounding slots: with selective SR only the M-1 partial sums and the clock draw
+    constexpr int NSLOT = !P::SR ? 0
+                          : (P::SELECTIVE ? M : Md::NPROP + (P::UNI ? (P::NORM ? 2 * M + 4 : M + 3) : 0));
     constexpr int SLOT_NORM = Md::NPROP;
-    constexpr int SLOT_SUM = Md::NPROP + (P::NORM ? M : 0);
+    constexpr int SLOT_SUM = P::SELECTIVE ? 0 : Md::NPROP + (P::NORM ? M : 0);
     constexpr int SLOT_LOG = SLOT_SUM + M - 1;
     constexpr int SLOT_TAU = SLOT_LOG + 1;
     constexpr int SLOT_TAUM = SLOT_TAU + 1;
-    constexpr int SLOT_TIME = SLOT_TAU + 1 + (P::NORM ? 1 : 0);
+    constexpr int SLOT_TIME = P::SELECTIVE ? M - 1 : SLOT_TAU + 1 + (P::NORM ? 1 : 0);
     constexpr int SLOT_TARGET = SLOT_TIME + 1;
 
     const T *rates = (const T *)I.rates;
@@ -330,6 +387,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     u64 n = 0;
     i32 k = 0;
     Tm t_next = 0;     // time of snapshot k (infinity past the last row of this launch)
+    Draw<P, NSLOT> cur;
+    u64 n_claim = 0;   // event index when this launch claimed the trajectory
     float mrun = 0.0f;
     u32 idx = 0;
     bool active = false;
@@ -352,8 +411,9 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     base = atomicAdd(I.counter, cnt);
                 base = __builtin_amdgcn_readlane(base, leader);
                 if (!active) {
-                    u32 id = base + rank_in(need);
-                    if (id < I.E) {
+                    u32 w = base + rank_in(need);
+                    if (w < I.E) {
+                        u32 id = I.order ? I.order[w] : w;
                         idx = id;
                         active = true;
                         if constexpr (PER_LANE_RATES) {
@@ -379,6 +439,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                             k = I.ck[id];
                             mrun = I.cm[id];
                             if (I.status[id] != ST_SUSPENDED) {
+                                if (I.work)
+                                    I.work[id] = 0u;
                                 // finished in an earlier chunk: fill this chunk's rows
                                 for (int kk = L.k_lo; kk < L.k_hi; ++kk)
 #pragma unroll
@@ -388,6 +450,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                             }
                         }
                         t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
+                        n_claim = n;
+                        cur = make_draw<P, NSLOT, SLOT_LOG>(n, I.id_base + id, L.seed_lo, L.seed_hi);
                     }
                 }
                 if (base + cnt >= I.E)
@@ -404,30 +468,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
         for (;;) {
             if (active) {
                 int status = -1;
-                // ---- random draws for event n
+                // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
-                W4 r0 = philox10((u32)n, (u32)(n >> 32), id, 0u, L.seed_lo, L.seed_hi);
-                Pool<NSLOT> pool;
-                if constexpr (NSLOT > 0) {
-                    pool.w[0] = r0.w2;
-                    pool.w[1] = r0.w3;
-#pragma unroll
-                    for (int q = 1; q < Pool<NSLOT>::NSTREAM; ++q) {
-                        W4 rq = philox10((u32)n, (u32)(n >> 32), id, (u32)q, L.seed_lo, L.seed_hi);
-                        pool.w[2 + 4 * (q - 1) + 0] = rq.w0;
-                        pool.w[2 + 4 * (q - 1) + 1] = rq.w1;
-                        pool.w[2 + 4 * (q - 1) + 2] = rq.w2;
-                        pool.w[2 + 4 * (q - 1) + 3] = rq.w3;
-                    }
-                }
-                A u1, u2;
-                if constexpr (P::WIDE) {
-                    u1 = unif53(r0.w0, r0.w1);
-                    u2 = unif53(r0.w2, r0.w3);
-                } else {
-                    u1 = unif24(r0.w0);
-                    u2 = unif24(r0.w1);
-                }
+                const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
+                const Pool<NSLOT> &pool = cur.pool;
                 // ---- propensities (generated op sequence)
                 T a[M];
                 Md::template propensities<P>(x, c, hill, a, pool);
@@ -465,16 +509,13 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                                  : (!(a0 > (A)0) ? ST_ABSORBED : -1);
                 // ---- waiting time and clock (formed on every lane, used only if the event fires)
                 Tm t_new;
-                if constexpr (P::WIDE) {
-                    t_new = t + neg_log64(u1) / a0;
-                } else if constexpr (P::UNI) {
-                    A lg = P::arnd(neg_log32(u1), pool.hw(SLOT_LOG));
-                    A tau = P::arnd(lg / a0, pool.hw(SLOT_TAU));
+                if constexpr (P::UNI) {
+                    A tau = P::arnd(cur.L / a0, pool.hw(SLOT_TAU));
                     if constexpr (P::NORM)
                         tau = P::arnd(tau / m, pool.hw(SLOT_TAUM));
-                    t_new = P::arnd(t + tau, pool.hw(SLOT_TIME));
+                    t_new = P::tacc(t + tau, pool.hw(SLOT_TIME));
                 } else {
-                    t_new = t + neg_log32(u1) / a0;
+                    t_new = t + cur.L / a0;
                 }
                 // ---- snapshots strictly before t_new hold the current state (rare)
                 if (status < 0 && t_next < t_new) {
@@ -491,7 +532,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                                            : ((!L.last && k >= L.k_hi) ? ST_SUSPENDED : -1);
                 const bool fire = status < 0;
                 // ---- selection and integer update (mu = M means no reaction fires)
-                A target = P::arnd(u2 * a0, pool.hw(SLOT_TARGET));
+                A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
                 int mu = 0, last_pos = 0;
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
@@ -504,6 +545,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 n += fire ? 1u : 0u;
                 if (fire && L.max_events && n == L.max_events)
                     status = ST_CAPPED;
+                cur = nxt;   // a lane that stops here draws afresh when it claims again
                 if (status >= 0) {
                     // ---- finish (or suspend) this trajectory
                     if (status != ST_SUSPENDED) {
@@ -515,6 +557,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                         I.t_last[idx] = (double)t;
                     }
                     I.status[idx] = (unsigned char)status;
+                    if (I.work)
+                        I.work[idx] = (u32)(n - n_claim);
                     if (!L.last) {
 #pragma unroll
                         for (int s = 0; s < N; ++s)
@@ -532,4 +576,54 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 break;
         }
     }
+}
+
+// --------------------------------------------------------------------------
+// Claim order for the next snapshot chunk: trajectories sorted by the events
+// they fired in the last chunk, heaviest first, in 256 log-spaced classes
+// (8 per octave). Waves then hold trajectories of similar length, and the
+// longest start first. Only the lane a trajectory runs on changes; its draws
+// are keyed by its id, so results are unchanged.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ u32 work_class(u32 w)
+{
+    u32 v = w + 1u;
+    u32 lz = 31u - (u32)__builtin_clz(v);                 // floor(log2 v)
+    u32 frac = lz >= 3u ? (v >> (lz - 3u)) & 7u : (v << (3u - lz)) & 7u;
+    u32 key = lz * 8u + frac;
+    return 255u - (key > 255u ? 255u : key);               // heaviest first
+}
+
+extern "C" __global__ void ssa_regroup_hist(const u32 *work, u32 E, u32 *hist)
+{
+    __shared__ u32 h[256];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < E; i += gridDim.x * blockDim.x)
+        atomicAdd(&h[work_class(work[i])], 1u);
+    __syncthreads();
+    if (h[threadIdx.x])
+        atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+extern "C" __global__ void ssa_regroup_scan(u32 *hist)
+{
+    // one workgroup of 256 threads: exclusive prefix sum in place
+    __shared__ u32 v[256];
+    const u32 t = threadIdx.x;
+    v[t] = hist[t];
+    __syncthreads();
+    for (u32 off = 1; off < 256u; off <<= 1) {
+        u32 add = t >= off ? v[t - off] : 0u;
+        __syncthreads();
+        v[t] += add;
+        __syncthreads();
+    }
+    hist[t] = t ? v[t - 1] : 0u;
+}
+
+extern "C" __global__ void ssa_regroup_scatter(const u32 *work, u32 E, u32 *offs, u32 *order)
+{
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < E; i += gridDim.x * blockDim.x)
+        order[atomicAdd(&offs[work_class(work[i])], 1u)] = i;
 }

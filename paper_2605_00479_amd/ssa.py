@@ -45,7 +45,8 @@ class ssa_run_desc(ctypes.Structure):
                 ("traj_id_base", ctypes.c_uint32), ("format", ctypes.c_int32), ("accum", ctypes.c_int32),
                 ("rounding", ctypes.c_int32), ("norm", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("max_events", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
-                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ssa_run_info(ctypes.Structure):
@@ -55,7 +56,12 @@ class ssa_run_info(ctypes.Structure):
                 ("total_events", ctypes.c_uint64)]
 
 
-EXPORTS = ("ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
+class ssa_tune_result(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_double)]
+
+
+EXPORTS = ("ssa_autotune", "ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
            "ssa_snapshots_get", "ssa_run_stats_get", "ssa_run_info_get", "ssa_run_destroy",
            "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source", "ssa_kernel_file")
 
@@ -68,6 +74,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2605_00479_amd.csrc.build`")
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # this library bind to that one, so the process holds a single HIP runtime.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, ctypes.POINTER(vp)]
@@ -85,6 +94,7 @@ def lib():
         L.ssa_prepare.argtypes = [ctypes.POINTER(ssa_run_desc)]
         L.ssa_dump_source.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p]
         L.ssa_kernel_file.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p, ctypes.c_size_t]
+        L.ssa_autotune.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.POINTER(ssa_tune_result)]
         _lib = L
     return _lib
 
@@ -95,14 +105,15 @@ def _check(rc):
 
 
 def parse_mode(name: str):
-    """FP64 / FP32 / {MIX,UNI}_{F16,BF16}_{RTN,SR}[_NORM] -> (format, accum, rounding, norm)."""
+    """FP64 / FP32 / {MIX,UNI}_{F16,BF16}_{RTN,SR,SRA}[_NORM] -> (format, accum, rounding, norm).
+    SRA: stochastic rounding at accumulation points only (uniform mode)."""
     if name in ("FP64", "FP32"):
         return FMT[name], 0, 0, 0
     parts = name.split("_")
     if len(parts) not in (3, 4) or parts[0] not in ("MIX", "UNI") or parts[1] not in ("F16", "BF16") \
-            or parts[2] not in ("RTN", "SR") or (len(parts) == 4 and parts[3] != "NORM"):
+            or parts[2] not in ("RTN", "SR", "SRA") or (len(parts) == 4 and parts[3] != "NORM"):
         raise ValueError(f"unknown precision mode {name!r}")
-    return FMT[parts[1]], int(parts[0] == "UNI"), int(parts[2] == "SR"), int(len(parts) == 4)
+    return FMT[parts[1]], int(parts[0] == "UNI"), {"RTN": 0, "SR": 1, "SRA": 2}[parts[2]], int(len(parts) == 4)
 
 
 class Model:
@@ -178,7 +189,7 @@ class Run:
 
 
 def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,
-          block_size=0, grid_size=0, stream=None, outputs=None):
+          block_size=0, grid_size=0, reorder=0, stream=None, outputs=None):
     """Build an ssa_run_desc. items: list of dicts with model (Model), x0, n_traj,
     optional set_rates [n_sets, M] and traj_per_set."""
     keep = {"arrays": [], "out": []}
@@ -221,11 +232,12 @@ def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_c
     d.hip_stream = stream
     d.block_size = int(block_size)
     d.grid_size = int(grid_size)
+    d.reorder = int(reorder)
     return d, keep
 
 
 def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,
-                     block_size=0, grid_size=0, torch_outputs=True) -> Run:
+                     block_size=0, grid_size=0, reorder=0, torch_outputs=True) -> Run:
     """Queue an ensemble run on torch's current stream. With torch_outputs the
     device outputs are torch tensors owned by the returned Run."""
     import torch
@@ -242,12 +254,22 @@ def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_
                             torch.empty(E, dtype=torch.uint8, device=dev)))
     stream = torch.cuda.current_stream().cuda_stream
     d, keep = _desc(items, t_end, snap_t, seed, mode, max_events=max_events, traj_id_base=traj_id_base,
-                    n_chunks=n_chunks, block_size=block_size, grid_size=grid_size, stream=stream,
-                    outputs=outputs)
+                    n_chunks=n_chunks, block_size=block_size, grid_size=grid_size, reorder=reorder,
+                    stream=stream, outputs=outputs)
     h = ctypes.c_void_p()
     _check(lib().ssa_ensemble_run(ctypes.byref(d), ctypes.byref(h)))
     meta = [(it["model"].n_species, int(it["n_traj"]), K) for it in items]
     return Run(h, meta, keep)
+
+
+def ssa_autotune(items, t_end, snap_t, seed, mode, **kw) -> dict:
+    """Time candidate launch shapes on this workload; the best is cached and used
+    by later runs that leave block_size / grid_size / n_chunks at 0."""
+    import torch
+    d, keep = _desc(items, t_end, snap_t, seed, mode, stream=torch.cuda.current_stream().cuda_stream, **kw)
+    res = ssa_tune_result()
+    _check(lib().ssa_autotune(ctypes.byref(d), ctypes.byref(res)))
+    return {f: getattr(res, f) for f, _ in ssa_tune_result._fields_}
 
 
 def ssa_prepare(items, t_end, snap_t, mode, **kw):
@@ -256,7 +278,7 @@ def ssa_prepare(items, t_end, snap_t, mode, **kw):
     _check(lib().ssa_prepare(ctypes.byref(d)))
 
 
-def ssa_kernel_file(items, t_end, snap_t, mode, **kw) -> str:
+def ssa_kernel_file(items, t_end, snap_t, mode, **kw) -> str:  # noqa: D401
     """Path of the cached code object a run description uses (compiles if needed)."""
     d, keep = _desc(items, t_end, snap_t, 0, mode, **kw)
     buf = ctypes.create_string_buffer(4096)

@@ -84,9 +84,12 @@ def test_run_descriptor_validation():
     assert _run_rc(_fields={"format": 9}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"accum": 1}) == ssa.SSA_E_INVALID            # FP64 + uniform
     assert _run_rc(mode="MIX_F16_SR", _fields={"norm": 1}) == ssa.SSA_E_UNSUPPORTED
+    assert _run_rc(mode="MIX_F16_SR", _fields={"rounding": 2}) == ssa.SSA_E_UNSUPPORTED
+    assert _run_rc(mode="UNI_F16_SR", _fields={"rounding": 3}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"block_size": 100}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"n_items": 0}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"traj_id_base": 2**32 - 5}) == ssa.SSA_E_INVALID
+    assert _run_rc(_fields={"reorder": 2}) == ssa.SSA_E_INVALID
     with pytest.raises(ValueError):
         ssa.parse_mode("MIX_F8_SR")
 
@@ -99,7 +102,7 @@ def test_negative_initial_count_rejected():
 
 @pytest.mark.parametrize("mode", ["FP64", "FP32", "MIX_F16_RTN", "MIX_F16_SR", "MIX_BF16_RTN", "MIX_BF16_SR",
                                   "UNI_F16_RTN", "UNI_F16_SR", "UNI_F16_SR_NORM", "UNI_BF16_RTN",
-                                  "UNI_BF16_SR", "UNI_BF16_SR_NORM"])
+                                  "UNI_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_SRA", "UNI_BF16_SRA_NORM"])
 def test_kernels_compile_for_every_mode(mode):
     W = wl.config_heterogeneous(100)
     items = ssa.items_from_workload(W)

@@ -71,7 +71,8 @@ def test_schlogl_modes(gpu, orc, mode):
 
 
 @pytest.mark.parametrize("mode", ["UNI_F16_RTN", "UNI_F16_SR", "UNI_F16_SR_NORM", "UNI_BF16_RTN",
-                                  "UNI_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_RTN_NORM", "FP64"])
+                                  "UNI_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_RTN_NORM", "FP64",
+                                  "UNI_F16_SRA", "UNI_BF16_SRA_NORM"])
 def test_telegraph_uniform_modes(gpu, orc, mode):
     W = wl.config_telegraph()
     it = W.items[0]
@@ -79,7 +80,7 @@ def test_telegraph_uniform_modes(gpu, orc, mode):
              max_events=W.max_events)
 
 
-@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR", "MIX_BF16_SR", "UNI_F16_SR"])
+@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR", "MIX_BF16_SR", "UNI_F16_SR", "UNI_BF16_SRA"])
 def test_repressilator_hill_laws(gpu, orc, mode):
     m = wl.repressilator()
     run_both(gpu, orc, m, np.array([0, 0, 0, 0, 0, 20], np.int32), 600, 60.0, wl.snapshot_grid(60.0, 61),
@@ -135,11 +136,12 @@ def test_chunked_graph_run_matches_single_launch(gpu, orc):
     for mode in ("FP64", "UNI_BF16_SR_NORM"):
         _, s1, st1 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
                               max_events=W.max_events)
-        _, s4, st4 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
-                              max_events=W.max_events, n_chunks=4)
-        np.testing.assert_array_equal(s1, s4)
-        for k in st1:
-            np.testing.assert_array_equal(st1[k], st4[k])
+        for reorder in (0, -1):
+            _, s4, st4 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
+                                  max_events=W.max_events, n_chunks=4, reorder=reorder)
+            np.testing.assert_array_equal(s1, s4)
+            for k in st1:
+                np.testing.assert_array_equal(st1[k], st4[k])
 
 
 def test_special_statuses(gpu, orc):
@@ -170,9 +172,10 @@ def test_multi_item_batch_matches_oracle_per_item(gpu, orc):
     t_end, ts = 15.0, wl.snapshot_grid(15.0, 16)
     models = {}
     items = gpu.items_from_workload(W, models)
-    for mode in ("FP64", "MIX_F16_SR", "MIX_BF16_SR"):
-        print(f"[gpu-parity] heterogeneous mode={mode}", flush=True)
-        run = gpu.ssa_ensemble_run(items, t_end, ts, 1, mode, traj_id_base=1000, max_events=W.max_events)
+    for mode, chunks in (("FP64", 1), ("MIX_F16_SR", 1), ("MIX_BF16_SR", 1), ("MIX_F16_SR", 3)):
+        print(f"[gpu-parity] heterogeneous mode={mode} chunks={chunks}", flush=True)
+        run = gpu.ssa_ensemble_run(items, t_end, ts, 1, mode, traj_id_base=1000, max_events=W.max_events,
+                                   n_chunks=chunks)
         base = 1000
         for i, it in enumerate(W.items):
             ref = orc.simulate(it.model, mode, it.x0, t_end, ts, 1, n_traj=it.n_traj, traj_id_base=base,

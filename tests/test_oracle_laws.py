@@ -314,6 +314,27 @@ def test_fp16_overflow_freezes_state(orc):
     assert np.all(r["status"] == 0)
 
 
+def test_paper_original_schlogl_fp16_overflow(orc):
+    """With the reservoirs A = 1e5, B = 2e5 as species entering the propensities
+    (the paper's original parameterisation), A exceeds fp16's range: every mixed
+    FP16 trajectory overflows at its first step and keeps X = 250, giving the
+    printed mean 250.0 and variance 0; bf16 has the range and does not overflow."""
+    from paper_2605_00479_amd.experiments import schlogl_with_reservoirs
+    m = schlogl_with_reservoirs()
+    mean_p, _ = golden("schlogl_original_mix_f16", "mean")
+    var_p, _ = golden("schlogl_original_mix_f16", "var")
+    for mode in ("MIX_F16_RTN", "MIX_F16_SR"):
+        r = run(orc, m, mode, [250, 100_000, 200_000], 10.0, [10.0], 500, seed=21)
+        x = r["snap"][0, 0]
+        assert np.all(r["status"] == 2) and x.mean() == mean_p and x.var() == var_p
+    r = run(orc, m, "MIX_BF16_SR", [250, 100_000, 200_000], 1.0, [1.0], 200, seed=21)
+    assert np.all(r["status"] == 0)
+    # in FP64 the reservoir form is the folded network's law
+    a = run(orc, m, "FP64", [250, 100_000, 200_000], 10.0, [10.0], 3000, seed=22)["snap"][0, 0]
+    b = run(orc, wl.schlogl(), "FP64", [250], 10.0, [10.0], 3000, seed=23)["snap"][0, 0]
+    assert stats.ks_2samp(a, b).pvalue > 1e-3
+
+
 def test_event_cap(orc):
     m = wl.birth_death(10.0, 0.1)
     r = run(orc, m, "UNI_BF16_RTN", [0], 100.0, [50.0, 100.0], 100, seed=15, max_events=300)
