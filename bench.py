@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--chunks", type=int, default=0, help="0: autotuned (or 1 without --no-autotune's tuning)")
     p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--valu-peak", action="store_true", help="also measure per-class VALU rates")
+    p.add_argument("--copy-calib", action="store_true",
+                   help="also run a 1 GiB device copy (calibrates the profiler's memory counters)")
     p.add_argument("--block", type=int, default=0)
     p.add_argument("--grid", type=int, default=0)
     return p.parse_args()
@@ -102,26 +104,69 @@ def timed_runs(ssa, items, W, mode, args, log):
             "marg": None if args.no_fidelity else marginals(last, W), "status_counts": status.tolist()}
 
 
-VALU_CLASSES = [("v_fma_f64", 1), ("v_fmamk_f32", 1), ("v_pk_fma_f16", 1), ("v_mad_u64_u32 + v_xor_b32", 5),
-                ("v_bitop3_b32", 1), ("v_cvt_sr_f16_f32 + v_cvt_f32_f16 + v_add_f32", 3), ("v_rcp_f32 + v_add_f32", 5)]
+VALU_CLASSES = ["v_add_u32", "v_bitop3_b32", "v_mad_u64_u32", "v_mul_f32", "v_fma_f32", "v_mul_f64", "v_fma_f64",
+                "v_rcp_f32", "v_rcp_f64", "v_cvt_sr_f16_f32 + v_cvt_f32_f16", "v_cvt_f16_f32 + v_cvt_f32_f16",
+                "v_add_f32", "v_add_f64", "v_cvt_f32_i32 + v_cvt_i32_f32", "v_mul_hi_u32 + v_or_b32", "v_cndmask_b32",
+                "v_add_f32 (VGPR operands)"]
+# (waves per SIMD, independent chains per lane): SIMD throughput, one wave's issue, dependent latency
+VALU_SHAPES = {"throughput_8w8c": (8, 8), "one_wave_8c": (1, 8), "latency_1w1c": (1, 1)}
 
 
 def valu_peak(log):
-    """Measured chain-step rates per instruction class; 'slots' is the weight the
-    roofline assumes for one step (quarter-rate ops = 4)."""
+    """Measured issue cost per instruction class: SIMD cycles per wave64 step
+    at the nominal 2.4 GHz (4 = one full-rate wave64 instruction on a SIMD16)."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_00479_amd", "libssa_valu_peak.so"))
-    lib.valu_peak_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                                  ctypes.POINTER(ctypes.c_double)]
+    lib.valu_peak_run_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    if lib.valu_peak_count() != len(VALU_CLASSES):
+        raise RuntimeError("libssa_valu_peak.so does not match bench.py's class list")
+    simd_lane_cycles = 256 * 4 * 2.4e9 * 64
     out = []
-    for op, (name, slots) in enumerate(VALU_CLASSES):
-        rate, ms = ctypes.c_double(), ctypes.c_double()
-        if lib.valu_peak_run(op, 4096, ctypes.byref(rate), ctypes.byref(ms)) != 0:
-            raise RuntimeError("valu_peak_run failed")
-        out.append({"class": name, "steps_per_s": rate.value, "assumed_slots": slots,
-                    "implied_slots_per_s": rate.value * slots, "ms": ms.value})
-        log(f"[bench] valu {name}: {rate.value:.3e} steps/s x {slots} slots = {rate.value * slots:.3e}")
+    for op, name in enumerate(VALU_CLASSES):
+        row = {"class": name}
+        for shape, (w, c) in VALU_SHAPES.items():
+            rate, ms = ctypes.c_double(), ctypes.c_double()
+            iters = 256 if w == 8 else 1024
+            if lib.valu_peak_run_shape(op, iters, w, c, ctypes.byref(rate), ctypes.byref(ms)) != 0:
+                raise RuntimeError("valu_peak_run_shape failed")
+            row[shape] = simd_lane_cycles / rate.value
+        out.append(row)
+        log(f"[bench] valu {name}: cycles/wave64 step " +
+            ", ".join(f"{k} {row[k]:.2f}" for k in VALU_SHAPES))
     return out
+
+
+def copy_calib(log, nbytes=1 << 30):
+    """One plain device-to-device copy of nbytes (kernel hbm_copy_kernel)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_00479_amd", "libssa_valu_peak.so"))
+    lib.hbm_copy_run.argtypes = [ctypes.c_size_t, ctypes.POINTER(ctypes.c_double)]
+    ms = ctypes.c_double()
+    if lib.hbm_copy_run(nbytes, ctypes.byref(ms)) != 0:
+        raise RuntimeError("hbm_copy_run failed")
+    gbs = 2 * nbytes / (ms.value * 1e-3) / 1e9
+    log(f"[bench] copy {nbytes} B: {ms.value:.3f} ms = {gbs:.0f} GB/s (read + write)")
+    return {"bytes": nbytes, "ms": ms.value, "GB_per_s_read_plus_write": gbs}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ssa_kernel_schlogl_100k_traffic.md")
+
+
+def measured_traffic(mode, kernel_file):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on this exact kernel object (rows: | mode | object | ... | bytes |)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    obj = os.path.basename(kernel_file)
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == mode and cells[1] == obj:
+            try:
+                return float(cells[-1])
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_baseline(W, mode, n_sample, log):
@@ -176,7 +221,7 @@ def main():
     # roofline: VALU slots of one event on the every-event path of the launched code object
     def per_event(mode):
         f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode)
-        return valu_count.count(f)
+        return {**valu_count.count(f), "file": f}
 
     ve, ve_ref = per_event(args.mode), per_event(args.ref_mode)
     ms = main_res["kernel_ms_avg"]
@@ -216,12 +261,16 @@ def main():
         "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
         "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                     "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
-                     "kernel": "ssa_kernel", "kernel_ms": ms, "valu_slots_per_event": ve["valu_slots"],
-                     "valu_insts_per_event": ve["valu_insts"]},
+                     "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS,
+                     "traffic": measured_traffic(args.mode, ve["file"]),
+                     "kernel": "ssa_kernel", "kernel_object": os.path.basename(ve["file"]), "kernel_ms": ms,
+                     "valu_slots_per_event": ve["valu_slots"], "valu_insts_per_event": ve["valu_insts"]},
     }
+    out["fp64"]["kernel_object"] = os.path.basename(ve_ref["file"])
     if args.valu_peak:
         out["valu_peak"] = valu_peak(log)
+    if args.copy_calib:
+        out["copy_calib"] = copy_calib(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.mode, args.cpu_sample, log)
     print(json.dumps(out))

@@ -149,7 +149,14 @@ typedef struct ssa_item {
  *   reorder: chunked runs only. 0 or 1: before each chunk after the first,
  *     trajectories are claimed in order of the events they fired in the
  *     previous chunk, heaviest first (results are unchanged: draws are keyed
- *     by trajectory id); -1: claim in id order. */
+ *     by trajectory id); -1: claim in id order.
+ *   first_window: chunked runs only. 0: the n_chunks windows split the
+ *     snapshot rows evenly. w > 0: the first window holds rows [0, w) and the
+ *     other n_chunks - 1 split the rest evenly; a short first window measures
+ *     each trajectory's event rate, so that with reorder the longest
+ *     trajectories start first in the next window. Must leave at least one row
+ *     for every later window (else SSA_E_INVALID). With n_chunks = 0 the
+ *     autotuned value is used. */
 typedef struct ssa_run_desc {
     const ssa_item *items;
     int32_t n_items;
@@ -168,7 +175,7 @@ typedef struct ssa_run_desc {
     int32_t block_size;
     int32_t grid_size;
     int32_t reorder;
-    int32_t reserved;
+    int32_t first_window;
 } ssa_run_desc;
 
 /* Start an ensemble run; returns once the work is queued on hip_stream
@@ -214,6 +221,7 @@ typedef struct ssa_tune_result {
     int32_t block_size;   /* threads per workgroup */
     int32_t grid_size;    /* workgroups: sets waves per CU and trajectories per lane */
     int32_t n_chunks;     /* snapshot windows (hipGraph-replayed launches) */
+    int32_t first_window; /* snapshot rows of the first window (0: even windows) */
     int32_t n_candidates; /* launch shapes timed */
     double best_ms;       /* device time of the chosen shape */
 } ssa_tune_result;
@@ -221,7 +229,8 @@ typedef struct ssa_tune_result {
 /* Launch-shape autotuner. Runs desc's workload (into scratch outputs owned by
  * the library; desc's output pointers are ignored) once per candidate shape:
  * block size 64 or 256; grid holding 1, 2 or 4 waves per SIMD with lane
- * refill, or one lane per trajectory; one launch or 4 snapshot chunks. Times
+ * refill, or one lane per trajectory; one launch, 4 even snapshot windows, or
+ * a first window of a tenth of the rows followed by 1 or 2 windows. Times
  * each with HIP events, keeps the fastest in memory and in
  * <cache dir>/tune.txt, keyed by the generated kernel and the workload shape
  * (ensemble sizes, snapshot count, t_end, max_events). Later runs of the same

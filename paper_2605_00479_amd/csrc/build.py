@@ -50,14 +50,20 @@ def build_library(verbose: bool = False) -> str:
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
     os.replace(LIB + ".tmp", LIB)
+    hip_shared(os.path.join(HERE, "valu_peak.hip"), PEAK_LIB)
+    return LIB
+
+
+def hip_shared(src: str, out: str) -> str:
+    """Compile one HIP source into a shared library for gfx950."""
     cmd = ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", *HIP_FLAGS,
-           os.path.join(HERE, "valu_peak.hip"), "-o", PEAK_LIB + ".tmp"]
+           src, "-o", out + ".tmp"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("building libssa_valu_peak.so failed")
-    os.replace(PEAK_LIB + ".tmp", PEAK_LIB)
-    return LIB
+        raise RuntimeError(f"building {os.path.basename(out)} failed")
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

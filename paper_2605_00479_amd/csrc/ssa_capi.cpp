@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -61,6 +62,7 @@ constexpr int kMaxSpecies = 32;
 constexpr int kMaxReactions = 64;
 constexpr int kMaxOrder = 4;
 constexpr int kMaxSnap = 65536;
+constexpr int kGraphMinChunks = 16;
 
 int64_t factorial(int n)
 {
@@ -193,9 +195,38 @@ std::string gen_model(const Model &md, int idx)
             slot = sl;
         }
     }
+    // x += nu_mu, mu in [0, M] (mu = M: nothing fires). A species whose net
+    // changes fit W-bit signed fields for all M + 1 values of mu reads its
+    // change from one packed constant with a single bitfield extract; any other
+    // species sums one select per reaction.
     o << "  }\n"
       << "  __device__ static __forceinline__ void update(i32 (&x)[N], int mu) {\n";
     for (int s = 0; s < md.N; ++s) {
+        int lo = 0, hi = 0;
+        for (int j = 0; j < md.M; ++j) {
+            int d = md.nu[(size_t)j * md.N + s];
+            lo = d < lo ? d : lo;
+            hi = d > hi ? d : hi;
+        }
+        if (lo == 0 && hi == 0)
+            continue;
+        int width = 0;
+        for (int w = 2; w <= 16; ++w) {
+            if (lo >= -(1 << (w - 1)) && hi <= (1 << (w - 1)) - 1 && (md.M + 1) * w <= 32) {
+                width = w;
+                break;
+            }
+        }
+        if (width) {
+            uint32_t pack = 0;
+            for (int j = 0; j < md.M; ++j) {
+                uint32_t field = (uint32_t)md.nu[(size_t)j * md.N + s] & ((1u << width) - 1u);
+                pack |= field << (j * width);
+            }
+            o << "    x[" << s << "] += __builtin_amdgcn_sbfe((i32)" << pack << "u, (u32)mu * " << width << "u, "
+              << width << "u);\n";
+            continue;
+        }
         std::string terms;
         for (int j = 0; j < md.M; ++j) {
             int d = md.nu[(size_t)j * md.N + s];
@@ -205,8 +236,7 @@ std::string gen_model(const Model &md, int idx)
                 terms += " + ";
             terms += "(mu == " + std::to_string(j) + " ? " + std::to_string(d) + " : 0)";
         }
-        if (!terms.empty())
-            o << "    x[" << s << "] += " << terms << ";\n";
+        o << "    x[" << s << "] += " << terms << ";\n";
     }
     o << "  }\n};\n";
     return o.str();
@@ -388,7 +418,7 @@ int get_kernel(const std::string &src, Loaded &out)
 // Launch shapes chosen by ssa_autotune, keyed by the kernel source and the
 // workload's shape, kept in memory and appended to <cache dir>/tune.txt.
 struct Tuned {
-    int block = 0, grid = 0, chunks = 0;
+    int block = 0, grid = 0, chunks = 0, window = 0;
     double ms = 0.0;
 };
 
@@ -411,10 +441,14 @@ void tune_load_locked()
         return;
     g_tune_loaded = true;
     std::ifstream in(cache_dir() + "/tune.txt");
-    std::string key;
-    Tuned t;
-    while (in >> key >> t.block >> t.grid >> t.chunks >> t.ms)
-        g_tuned[key] = t;
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        Tuned t;
+        if (ls >> key >> t.block >> t.grid >> t.chunks >> t.window >> t.ms)
+            g_tuned[key] = t;
+    }
 }
 
 bool tune_lookup(const std::string &key, Tuned &t)
@@ -436,7 +470,7 @@ void tune_store(const std::string &key, const Tuned &t)
     ::mkdir(cache_dir().c_str(), 0755);
     std::ofstream out(cache_dir() + "/tune.txt", std::ios::app);
     if (out)
-        out << key << " " << t.block << " " << t.grid << " " << t.chunks << " " << t.ms << "\n";
+        out << key << " " << t.block << " " << t.grid << " " << t.chunks << " " << t.window << " " << t.ms << "\n";
 }
 
 // ------------------------------------------------------------------ launch arguments
@@ -535,6 +569,10 @@ int validate_desc(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "grid_size must be >= 0");
     if (d->reorder < -1 || d->reorder > 1)
         return fail(SSA_E_INVALID, "reorder must be -1, 0 or 1");
+    if (d->first_window < 0)
+        return fail(SSA_E_INVALID, "first_window must be >= 0");
+    if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
+        return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
     uint64_t total = 0;
     for (int i = 0; i < d->n_items; ++i) {
         const ssa_item &it = d->items[i];
@@ -608,10 +646,11 @@ struct ssa_run {
     hipStream_t stream = nullptr;
     int K = 0;
     int n_launch = 0;
+    int first_window = 0;  // snapshot rows of the first chunk (0: even windows)
     int block = 0, grid = 0, vgprs = -1;
     bool graph = false;
     std::vector<ItemBuf> items;
-    std::vector<void *> owned;
+    std::vector<std::pair<void *, size_t>> owned;  // library-owned device buffers (returned to the cache)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> kev;  // start/stop per launch (non-graph runs)
     hipGraph_t g = nullptr;
@@ -624,20 +663,97 @@ struct ssa_run {
 
 namespace {
 
+// ------------------------------------------------------------------ buffer cache
+// The library's own device buffers (tables, carry state, claim order, counters
+// and outputs the caller does not provide) go back to a per-device free list
+// when a run is destroyed (after its work has finished) and are handed out
+// again to later runs, so repeated runs of one workload allocate nothing. At
+// most kCacheCap bytes are kept per device; the rest is freed.
+constexpr int kMaxDevices = 64;
+constexpr size_t kCacheCap = (size_t)1 << 30;
+
+struct BufCache {
+    std::mutex mu;
+    std::multimap<size_t, void *> free;
+    size_t bytes = 0;
+};
+BufCache g_cache[kMaxDevices];
+
+size_t cache_size_class(size_t bytes)
+{
+    return (bytes + 4095) & ~(size_t)4095;
+}
+
+// A cached block of at least `bytes` (and at most twice that), or NULL; its
+// size goes to *size.
+void *cache_take(int dev, size_t bytes, size_t *size)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return nullptr;
+    BufCache &c = g_cache[dev];
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free.lower_bound(bytes);
+    if (it == c.free.end() || it->first > 2 * bytes)
+        return nullptr;
+    void *p = it->second;
+    *size = it->first;
+    c.bytes -= it->first;
+    c.free.erase(it);
+    return p;
+}
+
+void cache_give(int dev, void *p, size_t bytes)
+{
+    if (dev >= 0 && dev < kMaxDevices) {
+        BufCache &c = g_cache[dev];
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.bytes + bytes <= kCacheCap) {
+            c.free.emplace(bytes, p);
+            c.bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
 template <class T>
 int dalloc(ssa_run *r, T **p, size_t n)
 {
     *p = nullptr;
     if (n == 0)
         return SSA_OK;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
-    if (e != hipSuccess)
-        return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE,
-                    std::string("hipMalloc: ") + hipGetErrorString(e));
-    r->owned.push_back(q);
+    const size_t want = cache_size_class(n * sizeof(T));
+    size_t got = want;
+    void *q = cache_take(r->device, want, &got);
+    if (!q) {
+        hipError_t e = hipMalloc(&q, want);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    r->owned.emplace_back(q, got);
     *p = (T *)q;
     return SSA_OK;
+}
+
+// Snapshot rows [k_lo, k_hi) of chunk c: with first_window w > 0 the first
+// chunk holds rows [0, w) and the others split [w, K) evenly; else all split
+// [0, K) evenly.
+void chunk_rows(int K, int n_chunks, int w, int c, int &k_lo, int &k_hi)
+{
+    if (w > 0 && n_chunks > 1) {
+        if (c == 0) {
+            k_lo = 0;
+            k_hi = w;
+            return;
+        }
+        const int64_t rest = K - w, m = n_chunks - 1;
+        k_lo = w + (int)((int64_t)(c - 1) * rest / m);
+        k_hi = c == n_chunks - 1 ? K : w + (int)((int64_t)c * rest / m);
+        return;
+    }
+    k_lo = (int)((int64_t)c * K / n_chunks);
+    k_hi = c == n_chunks - 1 ? K : (int)((int64_t)(c + 1) * K / n_chunks);
 }
 
 template <int NI>
@@ -663,8 +779,8 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
         HIP_TRY(hipModuleLaunchKernel(ld.fill, (n + 255) / 256, 1, 1, 256, 1, 1, 0, s, args, nullptr));
     }
     for (int c = 0; c < n_chunks; ++c) {
-        const int k_lo = (int)((int64_t)c * r->K / n_chunks);
-        const int k_hi = c == n_chunks - 1 ? r->K : (int)((int64_t)(c + 1) * r->K / n_chunks);
+        int k_lo, k_hi;
+        chunk_rows(r->K, n_chunks, r->first_window, c, k_lo, k_hi);
         A.h.k_lo = k_lo;
         A.h.k_hi = k_hi;
         A.h.first = c == 0;
@@ -752,27 +868,40 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
                             tune_lookup(tune_key(d, src), tuned);
     const bool wide = d->format == SSA_FMT_FP64;
     int n_chunks = d->n_chunks == 0 ? (have_tuned ? tuned.chunks : 1) : d->n_chunks;
+    int window = d->n_chunks == 0 ? (have_tuned ? tuned.window : 0) : d->first_window;
     if (n_chunks < 1)
         n_chunks = 1;
     if (n_chunks > std::max(r->K, 1))
         n_chunks = std::max(r->K, 1);
+    // the first window must leave at least one row for every later chunk
+    if (n_chunks < 2 || window < 0 || window > r->K - (n_chunks - 1))
+        window = 0;
+    r->first_window = window;
 
-    // snapshot times in both clock types
+    // All small tables (snapshot times in both clock types, and per item the
+    // rate table, Hill constants and x0) go to one device block in one copy.
+    std::vector<char> blob;
+    auto put = [&blob](const void *src, size_t n) {
+        size_t off = (blob.size() + 255) & ~(size_t)255;
+        blob.resize(off + n);
+        if (n)
+            std::memcpy(blob.data() + off, src, n);
+        return off;
+    };
     std::vector<float> t32(r->K);
     for (int k = 0; k < r->K; ++k)
         t32[k] = (float)d->snap_t[k];
-    if ((rc = dalloc(r, &r->t64, (size_t)r->K)) || (rc = dalloc(r, &r->t32, (size_t)r->K)))
-        return rc;
-    if (r->K) {
-        HIP_TRY(hipMemcpy(r->t64, d->snap_t, sizeof(double) * r->K, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(r->t32, t32.data(), sizeof(float) * r->K, hipMemcpyHostToDevice));
-    }
+    const size_t off_t64 = put(d->snap_t, sizeof(double) * r->K);
+    const size_t off_t32 = put(t32.data(), sizeof(float) * r->K);
+    struct ItemOffsets {
+        size_t rates, hill, x0;
+    };
+    std::vector<ItemOffsets> item_off;
     if ((rc = dalloc(r, &r->counters, (size_t)n_chunks * d->n_items)))
         return rc;
 
     uint64_t id_base = d->traj_id_base;
     int64_t total = 0;
-    std::vector<std::vector<char>> staging;  // host copies of the tables (uploaded synchronously)
     for (int i = 0; i < d->n_items; ++i) {
         const ssa_item &it = d->items[i];
         const Model &md = it.model->m;
@@ -788,8 +917,8 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         // rate table in the propensity type
         const int64_t n_sets = it.set_rates ? (per_lane ? it.n_sets : 1) : 1;
         const size_t tsz = wide ? sizeof(double) : sizeof(float);
-        staging.emplace_back((size_t)n_sets * md.M * tsz);
-        char *rt = staging.back().data();
+        std::vector<char> rtab((size_t)n_sets * md.M * tsz);
+        char *rt = rtab.data();
         for (int64_t sidx = 0; sidx < n_sets; ++sidx)
             for (int j = 0; j < md.M; ++j) {
                 double k = it.set_rates ? it.set_rates[sidx * md.M + j] : md.law[j].k;
@@ -799,8 +928,8 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
                 else
                     ((float *)rt)[sidx * md.M + j] = (float)v;
             }
-        staging.emplace_back((size_t)2 * md.M * tsz);
-        char *ht = staging.back().data();
+        std::vector<char> htab((size_t)2 * md.M * tsz);
+        char *ht = htab.data();
         for (int j = 0; j < md.M; ++j) {
             bool hill = md.law[j].kind != SSA_LAW_MASS_ACTION;
             double bv = to_prop_type(d->format, hill ? md.law[j].basal : 0.0);
@@ -813,15 +942,11 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
                 ((float *)ht)[2 * j + 1] = (float)kv;
             }
         }
-        char *rates_d = nullptr, *hill_d = nullptr;
-        if ((rc = dalloc(r, &rates_d, staging[staging.size() - 2].size())) ||
-            (rc = dalloc(r, &hill_d, staging.back().size())) || (rc = dalloc(r, &b.x0, (size_t)md.N)))
-            return rc;
-        HIP_TRY(hipMemcpy(rates_d, rt, staging[staging.size() - 2].size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(hill_d, ht, staging.back().size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b.x0, it.x0, sizeof(int32_t) * md.N, hipMemcpyHostToDevice));
-        b.rates = rates_d;
-        b.hill = hill_d;
+        ItemOffsets io;
+        io.rates = put(rtab.data(), rtab.size());
+        io.hill = put(htab.data(), htab.size());
+        io.x0 = put(it.x0, sizeof(int32_t) * md.N);
+        item_off.push_back(io);
         // outputs
         const size_t E = (size_t)it.n_traj;
         b.snap = it.d_snap;
@@ -846,6 +971,20 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         }
         r->items.push_back(b);
     }
+    {
+        char *base = nullptr;
+        if ((rc = dalloc(r, &base, blob.size())))
+            return rc;
+        if (!blob.empty())
+            HIP_TRY(hipMemcpy(base, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        r->t64 = (double *)(base + off_t64);
+        r->t32 = (float *)(base + off_t32);
+        for (int i = 0; i < d->n_items; ++i) {
+            r->items[i].rates = base + item_off[i].rates;
+            r->items[i].hill = base + item_off[i].hill;
+            r->items[i].x0 = (int32_t *)(base + item_off[i].x0);
+        }
+    }
 
     // launch shape: enough waves to cover the ensemble, at most what stays resident
     int cus = 0;
@@ -865,7 +1004,9 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     HIP_TRY(hipEventCreate(&r->ev0));
     HIP_TRY(hipEventCreate(&r->ev1));
     r->n_launch = n_chunks;
-    r->graph = n_chunks > 1;
+    // A captured graph pays off only over long chunk sequences: capture and
+    // instantiation cost more than a few direct launches.
+    r->graph = n_chunks > kGraphMinChunks;
     if (!r->graph) {
         r->kev.resize(2 * n_chunks);
         for (auto &e : r->kev)
@@ -915,8 +1056,8 @@ void release(ssa_run *r)
         (void)hipEventDestroy(r->ev0);
     if (r->ev1)
         (void)hipEventDestroy(r->ev1);
-    for (void *p : r->owned)
-        (void)hipFree(p);
+    for (auto &o : r->owned)
+        cache_give(r->device, o.first, o.second);
     delete r;
 }
 
@@ -1115,10 +1256,23 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
     for (int i = 0; i < desc->n_items; ++i)
         total += desc->items[i].n_traj;
     struct Cand {
-        int block, grid, chunks;
+        int block, grid, chunks, window;
     };
     std::vector<Cand> cands;
-    const int chunk_opts[] = {1, desc->n_snap >= 8 ? 4 : 1};
+    // one launch; 4 even windows; a first window of about a tenth of the rows
+    // (it measures every trajectory's event rate, so the longest start first)
+    // followed by one or two windows
+    struct ChunkOpt {
+        int chunks, window;
+    };
+    std::vector<ChunkOpt> chunk_opts = {{1, 0}};
+    if (desc->n_snap >= 8)
+        chunk_opts.push_back({4, 0});
+    if (desc->n_snap >= 10) {
+        const int w = std::max(1, desc->n_snap / 10);
+        chunk_opts.push_back({2, w});
+        chunk_opts.push_back({3, w});
+    }
     for (int block : {64, 256}) {
         int per_cu = 0;
         HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel, block, 0));
@@ -1136,12 +1290,13 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         std::sort(grids.begin(), grids.end());
         grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
         for (int64_t g : grids)
-            for (int ch : chunk_opts)
-                cands.push_back({block, (int)g, ch});
+            for (const ChunkOpt &ch : chunk_opts)
+                cands.push_back({block, (int)g, ch.chunks, ch.window});
     }
     cands.erase(std::unique(cands.begin(), cands.end(),
                             [](const Cand &a, const Cand &b) {
-                                return a.block == b.block && a.grid == b.grid && a.chunks == b.chunks;
+                                return a.block == b.block && a.grid == b.grid && a.chunks == b.chunks &&
+                                       a.window == b.window;
                             }),
                 cands.end());
     Tuned best;
@@ -1159,6 +1314,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         d2.block_size = c.block;
         d2.grid_size = c.grid;
         d2.n_chunks = c.chunks;
+        d2.first_window = c.window;
         ssa_run *r = new (std::nothrow) ssa_run;
         if (!r)
             return fail(SSA_E_NOMEM, "out of host memory");
@@ -1180,6 +1336,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
             best.block = c.block;
             best.grid = c.grid;
             best.chunks = c.chunks;
+            best.window = c.window;
             best.ms = ms;
         }
     }
@@ -1188,6 +1345,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         res->block_size = best.block;
         res->grid_size = best.grid;
         res->n_chunks = best.chunks;
+        res->first_window = best.window;
         res->best_ms = best.ms;
         res->n_candidates = (int32_t)cands.size();
     }

@@ -79,6 +79,27 @@ __device__ __forceinline__ float unif24(u32 w)
 }
 
 // --------------------------------------------------------------------------
+// Correctly rounded binary32 a / b (the IEEE quotient) for operands that need
+// no range scaling: a = 0 or 2^-26 <= |a| < 32, and 2^-24 <= b < 2^27. The
+// hardware reciprocal is refined by one Newton-Raphson step, then the quotient
+// by two remainder corrections (Markstein's fma division). On these ranges it
+// equals the full division sequence, which adds operand scaling and a
+// special-case fix-up (checked on the device over every log argument and
+// 2^28 numerators x 16 denominators); it saves three instructions per use.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float div_rn_inrange(float a, float b)
+{
+    float r = __builtin_amdgcn_rcpf(b);
+    float e = __builtin_fmaf(-b, r, 1.0f);
+    r = __builtin_fmaf(e, r, r);
+    float q = a * r;
+    float rem = __builtin_fmaf(-b, q, a);
+    q = __builtin_fmaf(rem, r, q);
+    rem = __builtin_fmaf(-b, q, a);
+    return __builtin_fmaf(rem, r, q);
+}
+
+// --------------------------------------------------------------------------
 // -ln(u), u in (0, 1]: u = 2^e f with f in [1/sqrt2, sqrt2],
 // ln f = 2 atanh(s) = 2s (1 + s^2/3 + s^4/5 + ...), s = (f - 1)/(f + 1),
 // e ln2 with ln2 split in a short high part (exact product) and a low part.
@@ -122,7 +143,7 @@ __device__ __forceinline__ float neg_log32(float u)
         f = f * 0.5f;
         e = e + 1;
     }
-    float s = (f - 1.0f) / (f + 1.0f);
+    float s = div_rn_inrange(f - 1.0f, f + 1.0f);   // |f - 1| < 0.42, f + 1 in [1.7, 2.5)
     float z = s * s;
     float p = 0x1.c71c72p-4f;                 // 1/9
     p = p * z + 0x1.24924ap-3f;               // 1/7
@@ -142,8 +163,9 @@ __device__ __forceinline__ float neg_log32(float u)
 // conversions (subnormals kept, overflow to infinity). Stochastic rounding
 // uses gfx950's SR conversions: with f the dropped fraction of a grid step,
 // the magnitude rounds up when the top B bits of the 16-bit halfword plus
-// floor(f 2^B) reach 2^B (B = 16 for bf16, 13 for fp16); the instructions read
-// their random bits from the upper half of the operand, hence rb << 16.
+// floor(f 2^B) reach 2^B (B = 16 for bf16, 13 for fp16). The instructions read
+// their random bits from the upper half of the 32-bit operand and ignore the
+// lower half, so `r` carries the slot's halfword in bits 31..16.
 // --------------------------------------------------------------------------
 typedef __bf16 ssa_v2bf16 __attribute__((ext_vector_type(2)));
 typedef _Float16 ssa_v2f16 __attribute__((ext_vector_type(2)));
@@ -158,18 +180,18 @@ __device__ __forceinline__ float rne_bf16(float v)
     return (float)(__bf16)v;
 }
 
-__device__ __forceinline__ float sr_bf16(float v, u32 rb)
+// The conversions write one 16-bit half of a register and keep the other; the
+// input's own bits serve as that other half, so no register needs clearing.
+__device__ __forceinline__ float sr_bf16(float v, u32 r)
 {
-    ssa_v2bf16 z = {};
-    ssa_v2bf16 r = __builtin_amdgcn_cvt_sr_bf16_f32(z, v, rb << 16, false);
-    return (float)r[0];
+    ssa_v2bf16 o = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(ssa_v2bf16, v), v, r, false);
+    return (float)o[0];
 }
 
-__device__ __forceinline__ float sr_f16(float v, u32 rb)
+__device__ __forceinline__ float sr_f16(float v, u32 r)
 {
-    ssa_v2f16 z = {};
-    ssa_v2f16 r = __builtin_amdgcn_cvt_sr_f16_f32(z, v, rb << 16, false);
-    return (float)r[0];
+    ssa_v2f16 o = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(ssa_v2f16, v), v, r, false);
+    return (float)o[0];
 }
 
 // --------------------------------------------------------------------------
@@ -190,6 +212,7 @@ struct PrecF64 {
     __device__ static A acc(A s, T a, u32) { return s + (A)a; }
     __device__ static A arnd(A v, u32) { return v; }
     __device__ static A tacc(A v, u32) { return v; }
+    __device__ static A tau_div(A l, A a0) { return l / a0; }
 };
 
 struct PrecF32 {
@@ -204,6 +227,7 @@ struct PrecF32 {
     __device__ static A acc(A s, T a, u32) { return s + a; }
     __device__ static A arnd(A v, u32) { return v; }
     __device__ static A tacc(A v, u32) { return v; }
+    __device__ static A tau_div(A l, A a0) { return l / a0; }
 };
 
 template <int FMT, bool SRM>
@@ -233,11 +257,24 @@ struct Prec16 {
     __device__ static A acc(A s, T a, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(s + a, rb) : s + a; }
     __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_OPS>(v, rb) : v; }
     __device__ static A tacc(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(v, rb) : v; }
+    // -ln(u1) / a0. With fp16 propensities a0 lies in [2^-24, 2^22] whenever
+    // the event can fire (any other value only sets a status), and
+    // -ln(u1) in {0} or [2^-24, 16.7]: the short division applies.
+    __device__ static A tau_div(A l, A a0)
+    {
+        if constexpr (FMT == FMT_FP16)
+            return div_rn_inrange(l, a0);
+        else
+            return l / a0;
+    }
 };
 
 // --------------------------------------------------------------------------
 // Rounding-halfword pool of one event: words 2, 3 of the stream-0 draw, then
-// four words from each further stream. Slot s is half (s & 1) of word s >> 1.
+// four words from each further stream. Slot s is half (s & 1) of word s >> 1
+// (half 0 = bits 15..0). hw(s) is the SR conversions' random operand for slot
+// s: the halfword in bits 31..16 (an odd slot's word as it is, since the
+// conversions ignore bits 15..0).
 // --------------------------------------------------------------------------
 template <int NSLOT>
 struct Pool {
@@ -249,7 +286,7 @@ struct Pool {
     {
         if (s >= 2 * NW)
             return 0u;
-        return (s & 1) ? (w[s >> 1] >> 16) : (w[s >> 1] & 0xFFFFu);
+        return (s & 1) ? w[s >> 1] : (w[s >> 1] << 16);
     }
 };
 
@@ -387,8 +424,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     u64 n = 0;
     i32 k = 0;
     Tm t_next = 0;     // time of snapshot k (infinity past the last row of this launch)
+    Tm t_stop = 0;     // an event at t_new fires only if t_new <= t_stop (-infinity: suspend)
     Draw<P, NSLOT> cur;
     u64 n_claim = 0;   // event index when this launch claimed the trajectory
+    const u64 n_stop = L.max_events ? L.max_events : ~0ull;
     float mrun = 0.0f;
     u32 idx = 0;
     bool active = false;
@@ -450,6 +489,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                             }
                         }
                         t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
+                        t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
                         n_claim = n;
                         cur = make_draw<P, NSLOT, SLOT_LOG>(n, I.id_base + id, L.seed_lo, L.seed_hi);
                     }
@@ -467,7 +507,6 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
 
         for (;;) {
             if (active) {
-                int status = -1;
                 // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
                 const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
@@ -477,20 +516,14 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 Md::template propensities<P>(x, c, hill, a, pool);
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
-                bool bad = false;
+                bool m_ok = true;
                 if constexpr (P::NORM) {
                     float mx = 0.0f;
 #pragma unroll
                     for (int j = 0; j < M; ++j)
                         mx = a[j] > mx ? a[j] : mx;
                     mrun = mx > mrun ? mx : mrun;
-                    if (!(mrun <= 3.40282347e38f)) {
-                        status = ST_OVERFLOW;
-                        bad = true;
-                    } else if (!(mrun > 0.0f)) {
-                        status = ST_ABSORBED;
-                        bad = true;
-                    }
+                    m_ok = mrun > 0.0f && mrun <= 3.40282347e38f;
                     m = mrun;
 #pragma unroll
                     for (int j = 0; j < M; ++j)
@@ -503,22 +536,25 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 for (int j = 1; j < M; ++j)
                     S[j] = P::acc(S[j - 1], a[j], pool.hw(SLOT_SUM + j - 1));
                 const A a0 = S[M - 1];
-                if (!bad)
-                    status = !(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
-                                 ? ST_OVERFLOW
-                                 : (!(a0 > (A)0) ? ST_ABSORBED : -1);
+                // a0 in (0, largest finite]: false for zero, negatives, infinity and NaN
+                bool a_ok;
+                if constexpr (P::WIDE)
+                    a_ok = a0 > 0.0 && a0 <= 1.7976931348623157e308;
+                else
+                    a_ok = __float_as_uint(a0) - 1u < 0x7F7FFFFFu;
+                a_ok = a_ok && m_ok;
                 // ---- waiting time and clock (formed on every lane, used only if the event fires)
                 Tm t_new;
                 if constexpr (P::UNI) {
-                    A tau = P::arnd(cur.L / a0, pool.hw(SLOT_TAU));
+                    A tau = P::arnd(P::tau_div(cur.L, a0), pool.hw(SLOT_TAU));
                     if constexpr (P::NORM)
                         tau = P::arnd(tau / m, pool.hw(SLOT_TAUM));
                     t_new = P::tacc(t + tau, pool.hw(SLOT_TIME));
                 } else {
-                    t_new = t + cur.L / a0;
+                    t_new = t + P::tau_div(cur.L, a0);
                 }
                 // ---- snapshots strictly before t_new hold the current state (rare)
-                if (status < 0 && t_next < t_new) {
+                if (a_ok && t_next < t_new) {
                     do {
 #pragma unroll
                         for (int s = 0; s < N; ++s)
@@ -526,28 +562,42 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                         ++k;
                         t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
                     } while (t_next < t_new);
+                    t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
                 }
-                if (status < 0)
-                    status = t_new > t_end ? ST_DONE
-                                           : ((!L.last && k >= L.k_hi) ? ST_SUSPENDED : -1);
-                const bool fire = status < 0;
-                // ---- selection and integer update (mu = M means no reaction fires)
-                A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
-                int mu = 0, last_pos = 0;
+                const bool fire = a_ok && t_new <= t_stop;
+                // ---- selection: mu = number of prefix sums at or below the target
+                const A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
+                int mu = 0;
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
+                for (int j = 0; j < M; ++j)
                     mu += (S[j] <= target) ? 1 : 0;
-                    last_pos = (a[j] > (T)0) ? j : last_pos;
+                if (__builtin_expect(mu == M, 0)) {
+                    // target at or above the total (rare): the last reaction with a positive propensity.
+                    // The empty asm keeps this a branch: speculated, it would cost 2M ops every event.
+                    __asm__ volatile("");
+                    int last_pos = 0;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        last_pos = (a[j] > (T)0) ? j : last_pos;
+                    mu = last_pos;
                 }
-                mu = mu == M ? last_pos : mu;
+                // ---- integer update (mu = M: nothing fires)
                 Md::update(x, fire ? mu : M);
                 t = fire ? t_new : t;
                 n += fire ? 1u : 0u;
-                if (fire && L.max_events && n == L.max_events)
-                    status = ST_CAPPED;
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
-                if (status >= 0) {
-                    // ---- finish (or suspend) this trajectory
+                if (!fire || n == n_stop) {
+                    // ---- finish (or suspend) this trajectory, once per trajectory
+                    int status;
+                    if (!a_ok)
+                        status = !m_ok ? (!(mrun <= 3.40282347e38f) ? ST_OVERFLOW : ST_ABSORBED)
+                                       : (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
+                                              ? ST_OVERFLOW
+                                              : ST_ABSORBED);
+                    else if (!fire)
+                        status = t_new > t_end ? ST_DONE : ST_SUSPENDED;
+                    else
+                        status = ST_CAPPED;
                     if (status != ST_SUSPENDED) {
                         for (; k < L.k_hi; ++k)
 #pragma unroll
@@ -622,8 +672,30 @@ extern "C" __global__ void ssa_regroup_scan(u32 *hist)
     hist[t] = t ? v[t - 1] : 0u;
 }
 
-extern "C" __global__ void ssa_regroup_scatter(const u32 *work, u32 E, u32 *offs, u32 *order)
+// Workgroups of 256 threads take tiles of 256 trajectories: ranks within a
+// class come from an LDS histogram of the tile and each (tile, class) reserves
+// its range with one global atomic. The order inside a class is arbitrary.
+extern "C" __global__ void __launch_bounds__(256) ssa_regroup_scatter(const u32 *work, u32 E, u32 *offs, u32 *order)
 {
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < E; i += gridDim.x * blockDim.x)
-        order[atomicAdd(&offs[work_class(work[i])], 1u)] = i;
+    __shared__ u32 cnt[256];
+    __shared__ u32 base[256];
+    const u32 t = threadIdx.x;
+    // the tile loop condition is the same for every thread of the workgroup
+    for (u32 tile = blockIdx.x * 256u; tile < E; tile += gridDim.x * 256u) {
+        cnt[t] = 0u;
+        __syncthreads();
+        const u32 i = tile + t;
+        u32 cls = 0u, rank = 0u;
+        if (i < E) {
+            cls = work_class(work[i]);
+            rank = atomicAdd(&cnt[cls], 1u);
+        }
+        __syncthreads();
+        if (cnt[t])
+            base[t] = atomicAdd(&offs[t], cnt[t]);
+        __syncthreads();
+        if (i < E)
+            order[base[cls] + rank] = i;
+        __syncthreads();
+    }
 }

@@ -6,8 +6,20 @@ multiplies (v_mad_u64_u32). Its every-event path is the set of blocks that
 path from that block back to the loop latch. Rare paths (snapshot stores,
 trajectory completion, the selection fallback, refills) are excluded by
 construction. Each VALU instruction on the path is weighted by its issue cost
-in full-rate lane slots: 4 for the quarter-rate integer multiplies and
-transcendental ops, 1 otherwise.
+in full-rate lane slots (one wave64 instruction on a 16-lane SIMD in 4 cycles
+= 1), by rate class. The classes are the ones libssa_valu_peak.so measures on
+MI355X at 8 waves per SIMD, relative to the full-rate classes (v_bitop3_b32,
+v_mad_u64_u32, f64 add/mul/fma, v_cndmask_b32: 4.3-4.8 cycles at the nominal
+2.4 GHz):
+  0.5  f32 add / sub / mul / fma and 32-bit integer add / sub (2.4-2.8
+       cycles with VGPR operands: the double-rate pipe; an SGPR operand makes
+       some of them full rate, so 0.5 is the lower bound of their cost and
+       the fraction of peak is never overstated);
+  2    f32 transcendentals (v_rcp_f32: 8.5 cycles) and the SR conversions
+       (v_cvt_sr_*: about 8 cycles);
+  4    f64 transcendentals (v_rcp_f64: 16.6 cycles);
+  1    everything else, including the 64-bit multiply-add Philox uses, which
+       issues at the full rate on gfx950.
 
 Usage: python -m paper_2605_00479_amd.csrc.valu_count <file.co>
 """
@@ -19,9 +31,21 @@ import sys
 
 OBJDUMP = "/opt/rocm/llvm/bin/llvm-objdump"
 
-QUARTER_RATE = re.compile(
-    r"^v_(mad_u64_u32|mad_i64_i32|mul_lo_u32|mul_hi_u32|mul_hi_i32|mul_lo_i32|rcp_|rsq_|sqrt_|log_|exp_|"
-    r"sin_|cos_|rcp_iflag)")
+_HALF = re.compile(r"^v_(mul_f32|fma_f32|fmac_f32|fmamk_f32|fmaak_f32|mac_f32|mad_f32|add_f32|sub_f32|subrev_f32|"
+                   r"add_u32|sub_u32|subrev_u32)")
+_TRANS64 = re.compile(r"^v_(rcp|rsq|sqrt)_f64")
+_DOUBLE = re.compile(r"^v_(rcp_|rsq_|sqrt_|log_|exp_|sin_|cos_|rcp_iflag|cvt_sr_)")
+
+
+def weight(op: str) -> float:
+    """Issue cost of one VALU instruction in full-rate lane slots."""
+    if _TRANS64.match(op):
+        return 4.0
+    if _DOUBLE.match(op):
+        return 2.0
+    if _HALF.match(op):
+        return 0.5
+    return 1.0
 
 _LINE = re.compile(r"^\s+(\S+)(.*?)//\s*([0-9A-Fa-f]+):.*?(?:<(\w+)\+0x([0-9a-f]+)>)?\s*$")
 
@@ -156,18 +180,19 @@ def event_path(co_path: str):
 
 def count(co_path: str) -> dict:
     blocks, path = event_path(co_path)
-    n_valu = n_slots = n_salu = 0
-    quarter = 0
+    n_valu = n_salu = 0
+    n_slots = 0.0
+    multi = 0
     for b in path:
         for _, op, _ in blocks[b]:
             if op.startswith("v_"):
-                w = 4 if QUARTER_RATE.match(op) else 1
+                w = weight(op)
                 n_valu += 1
                 n_slots += w
-                quarter += w == 4
+                multi += w > 1.0
             elif op.startswith("s_"):
                 n_salu += 1
-    return {"valu_insts": n_valu, "valu_slots": n_slots, "quarter_rate_insts": quarter, "salu_insts": n_salu,
+    return {"valu_insts": n_valu, "valu_slots": n_slots, "multi_cycle_insts": multi, "salu_insts": n_salu,
             "blocks": len(path)}
 
 

@@ -80,6 +80,14 @@ def experiments(scale: float = 1.0):
     }
 
 
+def prepare_experiment(ex: Experiment):
+    """Compile and cache every kernel the experiment launches (no GPU needed)."""
+    from . import ssa
+    item = [{"model": ssa.Model(ex.model), "x0": np.asarray(ex.x0, np.int32), "n_traj": ex.n_traj}]
+    for mode in ("FP64",) + tuple(ex.modes):
+        ssa.ssa_prepare(item, ex.t_end, [ex.t_end], mode, max_events=ex.max_events)
+
+
 def run_experiment(ex: Experiment, seed: int = 1, log=print):
     from . import ssa
     model = ssa.Model(ex.model)
@@ -137,9 +145,14 @@ def main(argv=None):
     p.add_argument("--only", default=None)
     p.add_argument("--scale", type=float, default=1.0)
     p.add_argument("--json", default=None)
+    p.add_argument("--prepare", action="store_true", help="only compile the kernels (no GPU needed)")
     a = p.parse_args(argv)
     exs = experiments(a.scale)
     names = [a.only] if a.only else list(exs)
+    if a.prepare:
+        for name in names:
+            prepare_experiment(exs[name])
+        return
     out = {}
     for name in names:
         rows = run_experiment(exs[name], log=lambda m: print(m, file=sys.stderr, flush=True))

@@ -90,6 +90,10 @@ def test_run_descriptor_validation():
     assert _run_rc(_fields={"n_items": 0}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"traj_id_base": 2**32 - 5}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"reorder": 2}) == ssa.SSA_E_INVALID
+    assert _run_rc(_fields={"first_window": -1}) == ssa.SSA_E_INVALID
+    # two snapshot rows cannot hold a first window of 2 and one more window
+    assert _run_rc(_fields={"n_chunks": 2, "first_window": 2}) == ssa.SSA_E_INVALID
+    assert _run_rc(_fields={"n_chunks": 2, "first_window": 1}) == ssa.SSA_OK
     with pytest.raises(ValueError):
         ssa.parse_mode("MIX_F8_SR")
 

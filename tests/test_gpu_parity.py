@@ -136,9 +136,9 @@ def test_chunked_graph_run_matches_single_launch(gpu, orc):
     for mode in ("FP64", "UNI_BF16_SR_NORM"):
         _, s1, st1 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
                               max_events=W.max_events)
-        for reorder in (0, -1):
+        for chunks, reorder, window in ((4, 0, 0), (4, -1, 0), (2, 0, 5), (3, 0, 1), (3, -1, 49)):
             _, s4, st4 = run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
-                                  max_events=W.max_events, n_chunks=4, reorder=reorder)
+                                  max_events=W.max_events, n_chunks=chunks, reorder=reorder, first_window=window)
             np.testing.assert_array_equal(s1, s4)
             for k in st1:
                 np.testing.assert_array_equal(st1[k], st4[k])
