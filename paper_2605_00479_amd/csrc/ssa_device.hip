@@ -75,7 +75,8 @@ __device__ __forceinline__ double unif53(u32 a, u32 b)
 
 __device__ __forceinline__ float unif24(u32 w)
 {
-    return (float)((w >> 8) + 1u) * 0x1p-24f;
+    // (m + 1) 2^-24 = m 2^-24 + 2^-24, exact in binary32 for m < 2^24
+    return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-24f);
 }
 
 // --------------------------------------------------------------------------
@@ -181,16 +182,17 @@ __device__ __forceinline__ float rne_bf16(float v)
 }
 
 // The conversions write one 16-bit half of a register and keep the other; the
-// input's own bits serve as that other half, so no register needs clearing.
+// random operand (used once, dead afterwards) serves as that other half, so no
+// register needs clearing or copying.
 __device__ __forceinline__ float sr_bf16(float v, u32 r)
 {
-    ssa_v2bf16 o = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(ssa_v2bf16, v), v, r, false);
+    ssa_v2bf16 o = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(ssa_v2bf16, r), v, r, false);
     return (float)o[0];
 }
 
 __device__ __forceinline__ float sr_f16(float v, u32 r)
 {
-    ssa_v2f16 o = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(ssa_v2f16, v), v, r, false);
+    ssa_v2f16 o = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(ssa_v2f16, r), v, r, false);
     return (float)o[0];
 }
 
@@ -243,6 +245,28 @@ __device__ __forceinline__ float rnd16(float v, u32 rb)
 // 2 stochastic rounding only where values accumulate (partial sums and the
 // clock, uniform mode), round to nearest elsewhere - the selective SR the
 // paper names as untested (Sec. 3.3, last paragraph).
+// binary32 a * b and a + b, each rounded once. For fp16 operands they are
+// written as fma(a, b, +0) and fma(a, 1, b) (equal to the product and the sum
+// for the non-negative values met here), which gfx950 runs as v_fma_mix_f32
+// reading the 16-bit halves directly, without a separate widening conversion.
+template <int FMT>
+__device__ __forceinline__ float mul32(float a, float b)
+{
+    if constexpr (FMT == FMT_FP16)
+        return __builtin_fmaf(a, b, 0.0f);
+    else
+        return a * b;
+}
+
+template <int FMT>
+__device__ __forceinline__ float add32(float a, float b)
+{
+    if constexpr (FMT == FMT_FP16)
+        return __builtin_fmaf(b, 1.0f, a);
+    else
+        return a + b;
+}
+
 template <int FMT, int RND, bool UNIF, bool NRM>
 struct Prec16 {
     typedef float T;
@@ -251,10 +275,13 @@ struct Prec16 {
     static constexpr bool SR = RND != 0, UNI = UNIF, NORM = NRM, WIDE = false, SELECTIVE = RND == 2;
     static constexpr bool SR_OPS = RND == 1, SR_ACC = RND != 0;
     __device__ static T cvt(i32 v, u32 rb) { return rnd16<FMT, SR_OPS>((float)v, rb); }
-    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a * b, rb); }
+    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(mul32<FMT>(a, b), rb); }
     __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a / b, rb); }
-    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a + b, rb); }
-    __device__ static A acc(A s, T a, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(s + a, rb) : s + a; }
+    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(add32<FMT>(a, b), rb); }
+    __device__ static A acc(A s, T a, u32 rb)
+    {
+        return UNIF ? rnd16<FMT, SR_ACC>(add32<FMT>(s, a), rb) : add32<FMT>(s, a);
+    }
     __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_OPS>(v, rb) : v; }
     __device__ static A tacc(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(v, rb) : v; }
     // -ln(u1) / a0. With fp16 propensities a0 lies in [2^-24, 2^22] whenever
@@ -506,6 +533,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
         }
 
         for (;;) {
+            bool stopped = false;
             if (active) {
                 // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
@@ -553,8 +581,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 } else {
                     t_new = t + P::tau_div(cur.L, a0);
                 }
-                // ---- snapshots strictly before t_new hold the current state (rare)
-                if (a_ok && t_next < t_new) {
+                // ---- snapshots strictly before t_new hold the current state (rare;
+                // the wave-uniform test lets the compiler place the stores out of line)
+                const bool snap_due = a_ok && t_next < t_new;
+                if (__builtin_expect(__ballot(snap_due) != 0, 0) && snap_due) {
                     do {
 #pragma unroll
                         for (int s = 0; s < N; ++s)
@@ -571,7 +601,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     mu += (S[j] <= target) ? 1 : 0;
-                if (__builtin_expect(mu == M, 0)) {
+                if (__builtin_expect(__ballot(mu == M) != 0, 0) && mu == M) {
                     // target at or above the total (rare): the last reaction with a positive propensity.
                     // The empty asm keeps this a branch: speculated, it would cost 2M ops every event.
                     __asm__ volatile("");
@@ -586,7 +616,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 t = fire ? t_new : t;
                 n += fire ? 1u : 0u;
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
-                if (!fire || n == n_stop) {
+                const bool stop = !fire || n == n_stop;
+                if (__builtin_expect(__ballot(stop) != 0, 0) && stop) {
                     // ---- finish (or suspend) this trajectory, once per trajectory
                     int status;
                     if (!a_ok)
@@ -619,11 +650,15 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                         I.cm[idx] = mrun;
                     }
                     active = false;
+                    stopped = true;
                 }
             }
-            u64 now = __ballot(active);
-            if (now == 0 || (open && now != act))
-                break;
+            // leave to claim new trajectories once a lane stops (while any are
+            // left), or when every lane has stopped
+            if (__builtin_expect(__ballot(stopped) != 0, 0)) {
+                if (open || __ballot(active) == 0)
+                    break;
+            }
         }
     }
 }

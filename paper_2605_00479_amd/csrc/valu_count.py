@@ -1,11 +1,10 @@
 """Count the VALU work of one event in a compiled ssa_kernel code object.
 
 The kernel's event loop is the innermost loop that contains the Philox
-multiplies (v_mad_u64_u32). Its every-event path is the set of blocks that
-(a) dominate the first Philox block from the loop header and (b) lie on every
-path from that block back to the loop latch. Rare paths (snapshot stores,
-trajectory completion, the selection fallback, refills) are excluded by
-construction. Each VALU instruction on the path is weighted by its issue cost
+multiplies (v_mad_u64_u32); one event is its lightest cycle through the block
+holding the next event's Philox calls (see event_paths). Rare paths (snapshot
+stores, trajectory completion, the selection fallback, refills) are excluded
+by construction. Each VALU instruction on the path is weighted by its issue cost
 in full-rate lane slots (one wave64 instruction on a 16-lane SIMD in 4 cycles
 = 1), by rate class. The classes are the ones libssa_valu_peak.so measures on
 MI355X at 8 waves per SIMD, relative to the full-rate classes (v_bitop3_b32,
@@ -139,12 +138,7 @@ def reachable(succ, root, allowed):
     return seen
 
 
-def event_path(co_path: str):
-    insts = disassemble(co_path)
-    blocks, order, succ = build_cfg(insts)
-    nodes = set(order)
-    dom = dominators(order, succ, order[0])
-    # natural loops from back edges
+def _natural_loops(order, succ, dom):
     loops = []
     for u in order:
         for v in succ[u]:
@@ -157,25 +151,82 @@ def event_path(co_path: str):
                         body.add(n)
                         stack.extend(p for p in order if n in succ[p])
                 loops.append((v, u, body))
+    # one loop per header: the union of its back edges' bodies
+    merged = {}
+    for h, _, body in loops:
+        merged[h] = merged.get(h, set()) | body
+    return merged
 
-    def is_mul(op):   # the Philox 32x32->64 multiplies (fused, or split into high/low halves)
-        return op in ("v_mad_u64_u32", "v_mul_hi_u32")
 
-    def n_mad(bs):
-        return sum(1 for b in bs for _, op, _ in blocks[b] if is_mul(op))
+def _is_mul(op):   # the Philox 32x32->64 multiplies (fused, or split into high/low halves)
+    return op in ("v_mad_u64_u32", "v_mul_hi_u32")
 
-    cands = [lp for lp in loops if n_mad(lp[2]) >= 18]
-    header, latch, body = min(cands, key=lambda lp: len(lp[2]))
-    first_mad = min((b for b in body if any(is_mul(op) for _, op, _ in blocks[b])))
-    # (a) blocks dominating the Philox entry from the header, inside the loop
-    sub = sorted(reachable(succ, header, body))
-    d_h = dominators(sub, {n: [s for s in succ[n] if s in body and s != header] for n in sub}, header)
-    pre = d_h[first_mad]
-    # (b) blocks on every path from the Philox entry to the latch
-    region = sorted(reachable({n: [s for s in succ[n] if s != header] for n in body}, first_mad, body))
-    d_e = dominators(region, {n: [s for s in succ[n] if s in region and s != header] for n in region}, first_mad)
-    path = pre | d_e[latch]
-    return blocks, sorted(path)
+
+def _slots(block):
+    return sum(weight(op) for _, op, _ in block if op.startswith("v_"))
+
+
+def event_paths(co_path: str):
+    """Lightest event of each copy of the event loop (the compiler may
+    unswitch it). For an innermost loop holding the next event's Philox calls,
+    B is its block with the most Philox multiplies; the event is the cycle from
+    B back to B with the fewest VALU slots (a shortest path with block
+    weights). Rare blocks (snapshot stores, trajectory completion, the
+    selection fallback, refills) are off that cycle, and where a wave-uniform
+    test picks one of two versions of a step, the lighter is counted, so the
+    work derived from it is never overstated."""
+    import heapq
+    insts = disassemble(co_path)
+    blocks, order, succ = build_cfg(insts)
+    dom = dominators(order, succ, order[0])
+    loops = _natural_loops(order, succ, dom)
+
+    def n_mul(bs):
+        return sum(1 for b in bs for _, op, _ in blocks[b] if _is_mul(op))
+
+    cands = {h: body for h, body in loops.items() if n_mul(body) >= 18}
+    # innermost: contains no other candidate's header
+    inner = {h: body for h, body in cands.items() if not any(h2 != h and h2 in body for h2 in cands)}
+    paths = []
+    for h, body in inner.items():
+        B = max(sorted(body), key=lambda b: sum(1 for _, op, _ in blocks[b] if _is_mul(op)))
+        # Dijkstra over blocks; cost of a path = slots of the blocks it enters
+        best = {B: _slots(blocks[B])}
+        prev = {}
+        heap = [(best[B], B)]
+        done = None
+        while heap:
+            c, n = heapq.heappop(heap)
+            if c > best.get(n, float("inf")):
+                continue
+            if n == -1:
+                done = c
+                break
+            for t in succ[n]:
+                if t not in body:
+                    continue
+                nxt, nc = (-1, c) if t == B else (t, c + _slots(blocks[t]))
+                if nc < best.get(nxt, float("inf")):
+                    best[nxt] = nc
+                    prev[nxt] = n
+                    heapq.heappush(heap, (nc, nxt))
+        if done is None:
+            continue
+        path, n = [], prev[-1]
+        while n != B:
+            path.append(n)
+            n = prev[n]
+        path.append(B)
+        paths.append(sorted(path))
+    if not paths:
+        raise RuntimeError("no event loop found in " + co_path)
+    return blocks, paths
+
+
+def event_path(co_path: str):
+    """The lightest event over the event loop's copies."""
+    blocks, paths = event_paths(co_path)
+    return blocks, min(paths, key=lambda p: sum(_slots(blocks[b]) for b in p))
 
 
 def count(co_path: str) -> dict:

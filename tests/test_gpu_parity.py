@@ -95,6 +95,22 @@ def test_dimer_parameter_sets_per_lane(gpu, orc, mode):
              seed=1, set_rate=rates, traj_per_set=40, max_events=3_000_000)
 
 
+@pytest.mark.parametrize("mode,levels", [("MIX_F16_SR", (1500.0, 2100.0, 2600.0)),
+                                         ("UNI_F16_SR", (1500.0, 2100.0, 2600.0)),
+                                         ("MIX_F16_RTN", (1500.0, 2100.0, 2600.0)),
+                                         ("MIX_BF16_SR", (180.0, 250.0, 330.0))])
+def test_count_conversion_across_exact_integer_limit(gpu, orc, mode, levels):
+    # Counts up to 2^11 (fp16) or 2^8 (bf16) convert exactly; above that the
+    # conversion itself rounds (by SR or RNE) and draws its rounding slot.
+    # Birth-death sets around the limit put lanes of one wave on both sides
+    # of it, and counts cross it during the run.
+    kd = 1.0
+    rates = np.array([[kb, kd] for kb in levels], np.float64)
+    start = np.int32(levels[1])
+    run_both(gpu, orc, wl.birth_death(levels[1], kd), np.array([start], np.int32), 3 * 70, 1.5,
+             wl.snapshot_grid(1.5, 7), mode, seed=11, set_rate=rates, traj_per_set=70, max_events=200_000)
+
+
 def test_self_repressor_activation_and_repression(gpu, orc):
     spec = wl._build("hill_pair", ["X", "Y"], [
         {"change": {"X": +1}, "hill": ("repress", "Y", 1.0, 40.0, 15.0, 3)},
