@@ -112,7 +112,17 @@ void ssa_model_destroy(ssa_model *model);
  *     i / traj_per_set (n_traj <= n_sets * traj_per_set). NULL: the model's k.
  *   d_snap, d_n_events, d_t_last, d_status: optional device outputs owned by
  *     the caller, laid out as [n_snap][N][n_traj] int32, [n_traj] uint64,
- *     [n_traj] double and [n_traj] uint8. NULL: the run allocates them. */
+ *     [n_traj] double and [n_traj] uint8. NULL: the run allocates them.
+ *   record_mask, record_cap: event record (the switching times behind the
+ *     dwell-time distributions of Sec. 4.3). Every firing of a reaction j with
+ *     bit j of record_mask set is logged with the clock after it (the run's
+ *     clock type, widened to double) and j, up to record_cap entries per
+ *     trajectory; the count of such firings goes on past record_cap. 0 / 0:
+ *     no record. record_cap in [0, 2^20], record_cap * n_traj <= 2^31.
+ *   d_rec_t, d_rec_j, d_rec_n: optional caller-owned device outputs of the
+ *     record, [n_traj][record_cap] double, [n_traj][record_cap] uint8 and
+ *     [n_traj] uint32 (entries past a trajectory's count are undefined). NULL:
+ *     the run allocates them. */
 typedef struct ssa_item {
     const ssa_model *model;
     const int32_t *x0;
@@ -124,6 +134,12 @@ typedef struct ssa_item {
     uint64_t *d_n_events;
     double *d_t_last;
     uint8_t *d_status;
+    uint64_t record_mask;
+    int32_t record_cap;
+    int32_t reserved;
+    double *d_rec_t;
+    uint8_t *d_rec_j;
+    uint32_t *d_rec_n;
 } ssa_item;
 
 /* An ensemble run over one or more items in one persistent launch.
@@ -201,6 +217,12 @@ int ssa_snapshots_get(const ssa_run *run, int32_t item, int32_t *dst, size_t dst
  * any pointer may be NULL. Waits for the run. */
 int ssa_run_stats_get(const ssa_run *run, int32_t item, uint64_t *n_events, double *t_last,
                       uint8_t *status, int dst_is_device);
+
+/* Copy item `item`'s event record to host or device memory (waits for the
+ * run): t and j [n_traj][record_cap] (entries past a trajectory's count are
+ * undefined), n [n_traj]; any pointer may be NULL. SSA_E_INVALID if the item
+ * has no record or is out of range. */
+int ssa_records_get(const ssa_run *run, int32_t item, double *t, uint8_t *j, uint32_t *n, int dst_is_device);
 
 /* Timing and launch facts of a finished run. */
 typedef struct ssa_run_info {

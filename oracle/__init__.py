@@ -53,6 +53,11 @@ class _Mode(ctypes.Structure):
                 ("norm", ctypes.c_int32)]
 
 
+class _Rec(ctypes.Structure):
+    _fields_ = [("mask", ctypes.c_uint64), ("cap", ctypes.c_int32), ("t", ctypes.c_void_p),
+                ("j", ctypes.c_void_p), ("n", ctypes.c_void_p)]
+
+
 class _Run(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_void_p), ("t_end", ctypes.c_double), ("snap_t", ctypes.c_void_p),
                 ("n_snap", ctypes.c_int32), ("seed", ctypes.c_uint64),
@@ -80,7 +85,8 @@ def _open(path):
     lib.or_simulate.restype = ctypes.c_int
     lib.or_simulate.argtypes = [ctypes.POINTER(_Model), _Mode, ctypes.POINTER(_Run),
                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(_Rec), ctypes.c_int32]
     for name in ("or_philox_batch", "or_nlog64_batch", "or_nlog32_batch", "or_uniform_batch"):
         getattr(lib, name).restype = None
     lib.or_round16_batch.restype = None
@@ -128,12 +134,16 @@ def _ptr(a):
 
 def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: int | None = None,
              indices=None, traj_id_base: int = 0, max_events: int = 0, set_rate=None,
-             traj_per_set: int = 0, threads: int = 1, lib=None):
+             traj_per_set: int = 0, threads: int = 1, record_mask: int = 0, record_cap: int = 0, lib=None):
     """Run trajectories ``indices`` (default ``range(n_traj)``) of an ensemble.
 
     Returns a dict with ``snap`` [K, N, count] int32, ``n_events`` uint64,
-    ``t_last`` float64 and ``status`` uint8 per trajectory. ``lib``: a library
-    from ``_open`` (default: the built oracle).
+    ``t_last`` float64 and ``status`` uint8 per trajectory; with a non-zero
+    ``record_mask`` (bit j: reaction j) also the event record: ``rec_t``
+    [count, record_cap] float64 (clock after each recorded firing), ``rec_j``
+    [count, record_cap] uint8 (reaction) and ``rec_n`` uint32 (recorded
+    firings, also those past ``record_cap``). ``lib``: a library from
+    ``_open`` (default: the built oracle).
     """
     lib = lib or _load()
     if indices is None:
@@ -168,11 +178,20 @@ def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: i
     n_ev = np.zeros(count, dtype=np.uint64)
     t_last = np.zeros(count, dtype=np.float64)
     status = np.zeros(count, dtype=np.uint8)
+    out = {"snap": snap, "n_events": n_ev, "t_last": t_last, "status": status}
+    rec = None
+    if record_mask:
+        cap = int(record_cap)
+        out["rec_t"] = np.zeros((count, cap), dtype=np.float64)
+        out["rec_j"] = np.zeros((count, cap), dtype=np.uint8)
+        out["rec_n"] = np.zeros(count, dtype=np.uint32)
+        rec = _Rec(int(record_mask) & (2**64 - 1), cap, _ptr(out["rec_t"]), _ptr(out["rec_j"]), _ptr(out["rec_n"]))
     rc = lib.or_simulate(ctypes.byref(md), cm, ctypes.byref(run), _ptr(idx), count, _ptr(snap),
-                         _ptr(n_ev), _ptr(t_last), _ptr(status), int(threads))
+                         _ptr(n_ev), _ptr(t_last), _ptr(status), ctypes.byref(rec) if rec else None,
+                         int(threads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
-    return {"snap": snap, "n_events": n_ev, "t_last": t_last, "status": status}
+    return out
 
 
 def philox(ctr, key, lib=None):

@@ -270,10 +270,23 @@ typedef struct {
     int64_t traj_per_set;
 } or_run;
 
+/* Event record: every firing of a reaction in `mask` is logged with the clock
+ * after it (widened to binary64) and the reaction index, up to `cap` records
+ * per trajectory; `n` counts all such firings, also those past `cap`. The
+ * switching times of a gene (Sec. 4.3 dwell times) are such a record. */
+typedef struct {
+    uint64_t mask;
+    int32_t cap;
+    double *t;               /* [count][cap] */
+    uint8_t *j;              /* [count][cap] */
+    uint32_t *n;             /* [count] */
+} or_rec;
+
 typedef struct {
     int32_t *snap;           /* [K][N][stride] */
     int64_t stride;
     int64_t col;
+    const or_rec *rec;       /* NULL: no record */
 } or_out;
 
 #define MAXM 64
@@ -300,6 +313,23 @@ static int reaction_ops(const or_model *md, int j)
     if (md->law[j] == LAW_HILL_REPRESS)
         return md->hill_h[j] + 4;
     return md->hill_h[j] + 5;
+}
+
+static void record(const or_out *o, uint32_t *cnt, int mu, double t)
+{
+    if (!o->rec || !((o->rec->mask >> mu) & 1u))
+        return;
+    if (*cnt < (uint32_t)o->rec->cap) {
+        o->rec->t[o->col * o->rec->cap + *cnt] = t;
+        o->rec->j[o->col * o->rec->cap + *cnt] = (uint8_t)mu;
+    }
+    ++*cnt;
+}
+
+static void finish_record(const or_out *o, uint32_t cnt)
+{
+    if (o->rec && o->rec->n)
+        o->rec->n[o->col] = cnt;
 }
 
 static void write_snap(const or_out *o, int k, int N, const int32_t *x)
@@ -362,6 +392,7 @@ static void traj_fp64(const or_model *md, const or_run *run, int64_t idx, const 
     double t = 0.0;
     uint64_t n = 0;
     int k = 0, status;
+    uint32_t rec_cnt = 0;
     for (;;) {
         uint32_t w[4];
         draw(run->seed, id, n, 0, w);
@@ -418,10 +449,12 @@ static void traj_fp64(const or_model *md, const or_run *run, int64_t idx, const 
             x[s] += md->nu[mu * N + s];
         t = t_new;
         ++n;
+        record(o, &rec_cnt, mu, (double)t);
         if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }
     }
     for (; k < K; ++k)
         write_snap(o, k, N, x);
+    finish_record(o, rec_cnt);
     *n_out = n;
     *t_out = t;
     *st_out = (uint8_t)status;
@@ -449,6 +482,7 @@ static void traj_fp32(const or_model *md, const or_run *run, int64_t idx, const 
     float t = 0.0f;
     uint64_t n = 0;
     int k = 0, status;
+    uint32_t rec_cnt = 0;
     for (;;) {
         uint32_t w[4];
         draw(run->seed, id, n, 0, w);
@@ -508,10 +542,12 @@ static void traj_fp32(const or_model *md, const or_run *run, int64_t idx, const 
             x[s] += md->nu[mu * N + s];
         t = t_new;
         ++n;
+        record(o, &rec_cnt, mu, (double)t);
         if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }
     }
     for (; k < K; ++k)
         write_snap(o, k, N, x);
+    finish_record(o, rec_cnt);
     *n_out = n;
     *t_out = (double)t;
     *st_out = (uint8_t)status;
@@ -610,6 +646,7 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
     float mx_run = 0.0f;
     uint64_t n = 0;
     int k = 0, status;
+    uint32_t rec_cnt = 0;
     sr_ctx ctx;
     rounder R = {mode.fmt, mode.sr == 1, &ctx};    /* propensity and other ops */
     rounder RA = {mode.fmt, mode.sr >= 1, &ctx};   /* partial sums and the clock */
@@ -706,10 +743,12 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
             x[s] += md->nu[mu * N + s];
         t = t_new;
         ++n;
+        record(o, &rec_cnt, mu, (double)t);
         if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }
     }
     for (; k < K; ++k)
         write_snap(o, k, N, x);
+    finish_record(o, rec_cnt);
     *n_out = n;
     *t_out = (double)t;
     *st_out = (uint8_t)status;
@@ -717,12 +756,13 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
 
 /* ------------------------------------------------------------------------- */
 /* Ensemble driver over a list of trajectory indices.                        */
-/* Outputs: snap [K][N][count], n_events/t_last/status [count].              */
+/* Outputs: snap [K][N][count], n_events/t_last/status [count], and with rec */
+/* the event record ([count][cap] times and reactions, [count] counts).      */
 /* Returns 0, or -1 for an argument the oracle does not handle.              */
 /* ------------------------------------------------------------------------- */
 int or_simulate(const or_model *md, or_mode mode, const or_run *run, const int64_t *idx,
                 int64_t count, int32_t *snap, uint64_t *n_events, double *t_last,
-                uint8_t *status, int32_t n_threads)
+                uint8_t *status, const or_rec *rec, int32_t n_threads)
 {
     if (md->n_species < 1 || md->n_species > MAXN || md->n_reactions < 1 ||
         md->n_reactions > MAXM || run->n_snap < 0)
@@ -733,12 +773,14 @@ int or_simulate(const or_model *md, or_mode mode, const or_run *run, const int64
         return -1;
     if (run->set_rate && run->traj_per_set < 1)
         return -1;
+    if (rec && (rec->cap < 0 || (rec->cap > 0 && (!rec->t || !rec->j)) || !rec->n))
+        return -1;
     if (n_threads < 1)
         n_threads = 1;
     int64_t i;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(n_threads)
     for (i = 0; i < count; ++i) {
-        or_out o = {snap, count, i};
+        or_out o = {snap, count, i, rec};
         if (mode.fmt == OR_FP64)
             traj_fp64(md, run, idx[i], &o, &n_events[i], &t_last[i], &status[i]);
         else if (mode.fmt == OR_FP32)

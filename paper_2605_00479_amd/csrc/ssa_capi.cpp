@@ -139,7 +139,7 @@ int reaction_slots(const Model &md, int j)
 
 // Device description of one network: propensity op sequence with its static
 // rounding slots, and the integer update x += nu_mu.
-std::string gen_model(const Model &md, int idx)
+std::string gen_model(const Model &md, int idx, uint64_t record_mask)
 {
     int nprop = 0;
     for (int j = 0; j < md.M; ++j)
@@ -147,6 +147,7 @@ std::string gen_model(const Model &md, int idx)
     std::ostringstream o;
     o << "struct Md" << idx << " {\n"
       << "  static constexpr int N = " << md.N << ", M = " << md.M << ", NPROP = " << nprop << ";\n"
+      << "  static constexpr u64 REC = " << record_mask << "ull;  // reactions whose firings are recorded\n"
       << "  template <class P, class PoolT>\n"
       << "  __device__ static __forceinline__ void propensities(const i32 (&x)[N], const typename P::T (&c)[M],"
       << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool) {\n"
@@ -258,12 +259,12 @@ struct ModeSpec {
 };
 
 std::string gen_source(const std::vector<const Model *> &models, const ModeSpec &ms,
-                       const std::vector<bool> &per_lane_rates)
+                       const std::vector<bool> &per_lane_rates, const std::vector<uint64_t> &record_masks)
 {
     std::ostringstream o;
     o << "#define SSA_N_ITEMS " << models.size() << "\n" << kDeviceSource << "\n";
     for (size_t i = 0; i < models.size(); ++i)
-        o << gen_model(*models[i], (int)i);
+        o << gen_model(*models[i], (int)i, record_masks[i]);
     o << "typedef " << ms.policy() << " PrecRun;\n"
       << "extern \"C\" __global__ void __launch_bounds__(256) ssa_kernel(LaunchArgs L) {\n"
       << "  const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n"
@@ -491,10 +492,13 @@ struct ItemArgsH {
     uint32_t *counter;
     const uint32_t *order;
     uint32_t *work;
+    double *rec_t;
+    unsigned char *rec_j;
+    uint32_t *rec_n;
     uint32_t E;
     uint32_t traj_per_set;
     uint32_t id_base;
-    uint32_t pad;
+    uint32_t rec_cap;
 };
 
 constexpr int kMaxItems = 8;
@@ -595,6 +599,13 @@ int validate_desc(const ssa_run_desc *d)
                 if (!(it.set_rates[r] >= 0.0) || !std::isfinite(it.set_rates[r]))
                     return fail(SSA_E_INVALID, "set_rates must be finite and >= 0");
         }
+        if (it.record_mask) {
+            if (it.record_cap < 0 || it.record_cap > (1 << 20) ||
+                (uint64_t)it.record_cap * (uint64_t)it.n_traj > ((uint64_t)1 << 31))
+                return fail(SSA_E_INVALID, "record_cap must be in [0, 2^20] with record_cap * n_traj <= 2^31");
+            if (it.model->m.M < 64 && (it.record_mask >> it.model->m.M) != 0)
+                return fail(SSA_E_INVALID, "record_mask names a reaction the model does not have");
+        }
         total += (uint64_t)it.n_traj;
     }
     if ((uint64_t)d->traj_id_base + total > 0xFFFFFFFFull)
@@ -607,12 +618,14 @@ int build_source(const ssa_run_desc *d, std::string &src)
 {
     std::vector<const Model *> models;
     std::vector<bool> per_lane;
+    std::vector<uint64_t> rec;
     for (int i = 0; i < d->n_items; ++i) {
         models.push_back(&d->items[i].model->m);
         per_lane.push_back(d->items[i].set_rates != nullptr && d->items[i].n_sets > 1);
+        rec.push_back(d->items[i].record_cap > 0 ? d->items[i].record_mask : 0ull);
     }
     ModeSpec ms{d->format, d->accum, d->rounding, d->norm};
-    src = gen_source(models, ms, per_lane);
+    src = gen_source(models, ms, per_lane, rec);
     return SSA_OK;
 }
 
@@ -637,6 +650,10 @@ struct ItemBuf {
     uint32_t *order = nullptr;   // claim order for the next chunk (chunked runs)
     uint32_t *work = nullptr;    // events per trajectory in the last chunk
     uint32_t *hist = nullptr;    // 256 work classes
+    double *rec_t = nullptr;     // event record [E][rec_cap]
+    uint8_t *rec_j = nullptr;
+    uint32_t *rec_n = nullptr;   // [E]; also the carry of the record count between chunks
+    uint32_t rec_cap = 0;
     uint32_t traj_per_set = 0;
     uint32_t id_base = 0;
 };
@@ -803,6 +820,10 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
             ia.counter = r->counters + (size_t)c * nI + i;
             ia.order = (c > 0 && b.order) ? b.order : nullptr;
             ia.work = b.work;
+            ia.rec_t = b.rec_t;
+            ia.rec_j = b.rec_j;
+            ia.rec_n = b.rec_n;
+            ia.rec_cap = b.rec_cap;
             ia.E = (uint32_t)b.E;
             ia.traj_per_set = b.traj_per_set;
             ia.id_base = b.id_base;
@@ -961,6 +982,16 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         b.status = it.d_status;
         if (!b.status && (rc = dalloc(r, &b.status, E)))
             return rc;
+        if (it.record_mask && it.record_cap > 0) {
+            b.rec_cap = (uint32_t)it.record_cap;
+            b.rec_t = it.d_rec_t;
+            b.rec_j = it.d_rec_j;
+            b.rec_n = it.d_rec_n;
+            const size_t cells = E * (size_t)it.record_cap;
+            if ((!b.rec_t && (rc = dalloc(r, &b.rec_t, cells))) || (!b.rec_j && (rc = dalloc(r, &b.rec_j, cells))) ||
+                (!b.rec_n && (rc = dalloc(r, &b.rec_n, E))))
+                return rc;
+        }
         if (n_chunks > 1) {
             if ((rc = dalloc(r, &b.cx, (size_t)md.N * E)) || (rc = dalloc(r, &b.ct, E)) ||
                 (rc = dalloc(r, &b.cn, E)) || (rc = dalloc(r, &b.ck, E)) || (rc = dalloc(r, &b.cm, E)))
@@ -1196,6 +1227,27 @@ int ssa_run_stats_get(const ssa_run *run, int32_t item, uint64_t *n_events, doub
     return SSA_OK;
 }
 
+int ssa_records_get(const ssa_run *run, int32_t item, double *t, uint8_t *j, uint32_t *n, int dst_is_device)
+{
+    if (!run || item < 0 || item >= (int)run->items.size())
+        return fail(SSA_E_INVALID, "run is NULL or item out of range");
+    const ItemBuf &b = run->items[item];
+    if (!b.rec_n)
+        return fail(SSA_E_INVALID, "the item has no event record");
+    const size_t E = (size_t)b.E, cells = E * b.rec_cap;
+    if (E == 0)
+        return SSA_OK;
+    HIP_TRY(hipEventSynchronize(run->ev1));
+    hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (t && cells)
+        HIP_TRY(hipMemcpy(t, b.rec_t, cells * sizeof(double), kind));
+    if (j && cells)
+        HIP_TRY(hipMemcpy(j, b.rec_j, cells * sizeof(uint8_t), kind));
+    if (n)
+        HIP_TRY(hipMemcpy(n, b.rec_n, E * sizeof(uint32_t), kind));
+    return SSA_OK;
+}
+
 int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
 {
     if (!run || !info)
@@ -1309,6 +1361,9 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
             it.d_n_events = nullptr;
             it.d_t_last = nullptr;
             it.d_status = nullptr;
+            it.d_rec_t = nullptr;
+            it.d_rec_j = nullptr;
+            it.d_rec_n = nullptr;
         }
         d2.items = items.data();
         d2.block_size = c.block;

@@ -376,10 +376,13 @@ struct ItemArgs {
     u32 *counter;            // work counter of this item (starts at 0)
     const u32 *order;        // claim order: trajectory of the w-th claim (NULL: w itself)
     u32 *work;               // events each trajectory fired in this launch (NULL: not recorded)
+    double *rec_t;           // event record [E][rec_cap]: clock after each recorded firing
+    unsigned char *rec_j;    // [E][rec_cap]: the reaction
+    u32 *rec_n;              // [E]: recorded firings so far (also carried between chunks)
     u32 E;                   // trajectories
     u32 traj_per_set;        // trajectories per rate set (0: one set)
     u32 id_base;             // Philox trajectory id of trajectory 0
-    u32 pad;
+    u32 rec_cap;             // records kept per trajectory
 };
 
 struct LaunchArgs {
@@ -454,6 +457,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     Tm t_stop = 0;     // an event at t_new fires only if t_new <= t_stop (-infinity: suspend)
     Draw<P, NSLOT> cur;
     u64 n_claim = 0;   // event index when this launch claimed the trajectory
+    u32 rec_cnt = 0;   // recorded firings of this trajectory (Md::REC reactions)
     const u64 n_stop = L.max_events ? L.max_events : ~0ull;
     float mrun = 0.0f;
     u32 idx = 0;
@@ -496,6 +500,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                             n = 0;
                             k = 0;
                             mrun = 0.0f;
+                            rec_cnt = 0;
                         } else {
 #pragma unroll
                             for (int s = 0; s < N; ++s)
@@ -504,6 +509,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                             n = I.cn[id];
                             k = I.ck[id];
                             mrun = I.cm[id];
+                            if constexpr (Md::REC != 0)
+                                rec_cnt = I.rec_n[id];
                             if (I.status[id] != ST_SUSPENDED) {
                                 if (I.work)
                                     I.work[id] = 0u;
@@ -615,6 +622,16 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 Md::update(x, fire ? mu : M);
                 t = fire ? t_new : t;
                 n += fire ? 1u : 0u;
+                if constexpr (Md::REC != 0) {
+                    // event record: firings of the recorded reactions, with the clock after them
+                    if (fire && ((Md::REC >> mu) & 1ull)) {
+                        if (rec_cnt < I.rec_cap) {
+                            I.rec_t[(u64)idx * I.rec_cap + rec_cnt] = (double)t;
+                            I.rec_j[(u64)idx * I.rec_cap + rec_cnt] = (unsigned char)mu;
+                        }
+                        ++rec_cnt;
+                    }
+                }
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
                 const bool stop = !fire || n == n_stop;
                 if (__builtin_expect(__ballot(stop) != 0, 0) && stop) {
@@ -640,6 +657,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     I.status[idx] = (unsigned char)status;
                     if (I.work)
                         I.work[idx] = (u32)(n - n_claim);
+                    if constexpr (Md::REC != 0)
+                        I.rec_n[idx] = rec_cnt;
                     if (!L.last) {
 #pragma unroll
                         for (int s = 0; s < N; ++s)

@@ -36,7 +36,9 @@ class ssa_item(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("n_traj", ctypes.c_int64),
                 ("set_rates", ctypes.c_void_p), ("n_sets", ctypes.c_int64), ("traj_per_set", ctypes.c_int64),
                 ("d_snap", ctypes.c_void_p), ("d_n_events", ctypes.c_void_p), ("d_t_last", ctypes.c_void_p),
-                ("d_status", ctypes.c_void_p)]
+                ("d_status", ctypes.c_void_p), ("record_mask", ctypes.c_uint64), ("record_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("d_rec_t", ctypes.c_void_p), ("d_rec_j", ctypes.c_void_p),
+                ("d_rec_n", ctypes.c_void_p)]
 
 
 class ssa_run_desc(ctypes.Structure):
@@ -63,7 +65,8 @@ class ssa_tune_result(ctypes.Structure):
 
 EXPORTS = ("ssa_autotune", "ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
            "ssa_snapshots_get", "ssa_run_stats_get", "ssa_run_info_get", "ssa_run_destroy",
-           "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source", "ssa_kernel_file")
+           "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source", "ssa_kernel_file",
+           "ssa_records_get")
 
 _lib = None
 
@@ -86,6 +89,7 @@ def lib():
         L.ssa_run_wait.argtypes = [vp]
         L.ssa_snapshots_get.argtypes = [vp, i32, vp, ctypes.c_size_t, ctypes.c_int]
         L.ssa_run_stats_get.argtypes = [vp, i32, vp, vp, vp, ctypes.c_int]
+        L.ssa_records_get.argtypes = [vp, i32, vp, vp, vp, ctypes.c_int]
         L.ssa_run_info_get.argtypes = [vp, ctypes.POINTER(ssa_run_info)]
         L.ssa_run_destroy.argtypes = [vp]
         L.ssa_run_destroy.restype = None
@@ -146,10 +150,11 @@ class Model:
 class Run:
     """A queued ensemble run; results are read through the C ABI getters."""
 
-    def __init__(self, handle, items, keep):
+    def __init__(self, handle, items, keep, record_caps=None):
         self.handle = handle
-        self.items = items     # list of (N, E)
+        self.items = items     # list of (N, E, K)
         self._keep = keep      # host arrays and output tensors referenced by the run
+        self.record_caps = record_caps or [0] * len(items)
 
     def wait(self):
         _check(lib().ssa_run_wait(self.handle))
@@ -167,6 +172,18 @@ class Run:
         st = np.empty(E, dtype=np.uint8)
         _check(lib().ssa_run_stats_get(self.handle, item, nev.ctypes.data, tl.ctypes.data, st.ctypes.data, 0))
         return {"n_events": nev, "t_last": tl, "status": st}
+
+    def records(self, item: int = 0) -> dict:
+        """The item's event record: ``t`` [E, cap] float64 (clock after each
+        recorded firing), ``j`` [E, cap] uint8 (reaction) and ``n`` [E]
+        uint32 (recorded firings, also those past cap)."""
+        N, E, K = self.items[item]
+        cap = self.record_caps[item]
+        t = np.empty((E, cap), dtype=np.float64)
+        j = np.empty((E, cap), dtype=np.uint8)
+        n = np.empty(E, dtype=np.uint32)
+        _check(lib().ssa_records_get(self.handle, item, t.ctypes.data, j.ctypes.data, n.ctypes.data, 0))
+        return {"t": t, "j": j, "n": n}
 
     def info(self) -> dict:
         inf = ssa_run_info()
@@ -191,7 +208,8 @@ class Run:
 def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,
           block_size=0, grid_size=0, reorder=0, first_window=0, stream=None, outputs=None):
     """Build an ssa_run_desc. items: list of dicts with model (Model), x0, n_traj,
-    optional set_rates [n_sets, M] and traj_per_set."""
+    optional set_rates [n_sets, M] and traj_per_set, optional record =
+    (reaction mask, records per trajectory)."""
     keep = {"arrays": [], "out": []}
     arr = (ssa_item * len(items))()
     for i, it in enumerate(items):
@@ -208,6 +226,10 @@ def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_c
             arr[i].set_rates = sr.ctypes.data
             arr[i].n_sets = sr.shape[0]
             arr[i].traj_per_set = int(it["traj_per_set"])
+        rec = it.get("record")
+        if rec is not None:
+            arr[i].record_mask = int(rec[0]) & (2**64 - 1)
+            arr[i].record_cap = int(rec[1])
         if outputs is not None:
             o = outputs[i]
             keep["out"].append(o)
@@ -215,6 +237,10 @@ def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_c
             arr[i].d_n_events = o[1].data_ptr() if o[1].numel() else None
             arr[i].d_t_last = o[2].data_ptr() if o[2].numel() else None
             arr[i].d_status = o[3].data_ptr() if o[3].numel() else None
+            if len(o) > 4:
+                arr[i].d_rec_t = o[4].data_ptr() if o[4].numel() else None
+                arr[i].d_rec_j = o[5].data_ptr() if o[5].numel() else None
+                arr[i].d_rec_n = o[6].data_ptr() if o[6].numel() else None
     ts = np.ascontiguousarray(snap_t, dtype=np.float64)
     keep["arrays"] += [ts, arr]
     fmt, acc, rnd, norm = parse_mode(mode)
@@ -249,10 +275,17 @@ def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_
         outputs = []
         for it in items:
             N, E = it["model"].n_species, int(it["n_traj"])
-            outputs.append((torch.empty((K, N, E), dtype=torch.int32, device=dev),
-                            torch.empty(E, dtype=torch.int64, device=dev),
-                            torch.empty(E, dtype=torch.float64, device=dev),
-                            torch.empty(E, dtype=torch.uint8, device=dev)))
+            o = (torch.empty((K, N, E), dtype=torch.int32, device=dev),
+                 torch.empty(E, dtype=torch.int64, device=dev),
+                 torch.empty(E, dtype=torch.float64, device=dev),
+                 torch.empty(E, dtype=torch.uint8, device=dev))
+            rec = it.get("record")
+            if rec is not None and int(rec[0]) and int(rec[1]) > 0:
+                cap = int(rec[1])
+                o = o + (torch.empty((E, cap), dtype=torch.float64, device=dev),
+                         torch.empty((E, cap), dtype=torch.uint8, device=dev),
+                         torch.empty(E, dtype=torch.int32, device=dev))
+            outputs.append(o)
     stream = torch.cuda.current_stream().cuda_stream
     d, keep = _desc(items, t_end, snap_t, seed, mode, max_events=max_events, traj_id_base=traj_id_base,
                     n_chunks=n_chunks, block_size=block_size, grid_size=grid_size, reorder=reorder,
@@ -260,7 +293,8 @@ def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_
     h = ctypes.c_void_p()
     _check(lib().ssa_ensemble_run(ctypes.byref(d), ctypes.byref(h)))
     meta = [(it["model"].n_species, int(it["n_traj"]), K) for it in items]
-    return Run(h, meta, keep)
+    caps = [int(it["record"][1]) if it.get("record") is not None and int(it["record"][0]) else 0 for it in items]
+    return Run(h, meta, keep, caps)
 
 
 def ssa_autotune(items, t_end, snap_t, seed, mode, **kw) -> dict:

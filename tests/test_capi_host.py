@@ -98,6 +98,22 @@ def test_run_descriptor_validation():
         ssa.parse_mode("MIX_F8_SR")
 
 
+def test_record_arguments_validated():
+    m = ssa.Model(wl.telegraph(0.05, 0.05, 20.0, 1.0))
+
+    def rc(mask, cap, n=10):
+        d, keep = ssa._desc([{"model": m, "x0": [1, 0, 0], "n_traj": n, "record": (mask, cap)}], 1.0, [1.0], 1,
+                            "FP64")
+        return ssa.lib().ssa_prepare(ctypes.byref(d))
+
+    assert rc(0b11, 16) == ssa.SSA_OK
+    assert rc(0, 0) == ssa.SSA_OK
+    assert rc(0b11, -1) == ssa.SSA_E_INVALID
+    assert rc(0b11, (1 << 20) + 1) == ssa.SSA_E_INVALID
+    assert rc(0b11, 1 << 20, n=4096) == ssa.SSA_E_INVALID       # cap * n_traj > 2^31
+    assert rc(1 << 4, 16) == ssa.SSA_E_INVALID                    # the telegraph has 4 reactions
+
+
 def test_negative_initial_count_rejected():
     m = ssa.Model(wl.birth_death())
     d, keep = ssa._desc([{"model": m, "x0": [-1], "n_traj": 4}], 1.0, [1.0], 1, "FP64")

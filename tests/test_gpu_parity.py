@@ -111,6 +111,64 @@ def test_count_conversion_across_exact_integer_limit(gpu, orc, mode, levels):
              wl.snapshot_grid(1.5, 7), mode, seed=11, set_rate=rates, traj_per_set=70, max_events=200_000)
 
 
+def run_records(gpu, orc, spec, x0, n, t_end, snap_t, mode, mask, cap, *, seed=1, **launch):
+    m = gpu.Model(spec)
+    item = {"model": m, "x0": x0, "n_traj": n, "record": (mask, cap)}
+    print(f"[gpu-parity] records {spec.name} mode={mode} n={n} mask={mask} cap={cap} launch={launch}", flush=True)
+    run = gpu.ssa_ensemble_run([item], t_end, snap_t, seed, mode, **launch)
+    rec = run.records(0)
+    ref = orc.simulate(spec, mode, x0, t_end, snap_t, seed, n_traj=n, record_mask=mask, record_cap=cap,
+                       threads=ORACLE_THREADS)
+    assert_parity(ref, run.snapshots(0), run.stats(0), mode, spec.name)
+    np.testing.assert_array_equal(rec["n"], ref["rec_n"])
+    for i in range(n):
+        k = min(int(ref["rec_n"][i]), cap)
+        np.testing.assert_array_equal(rec["j"][i, :k], ref["rec_j"][i, :k])
+        np.testing.assert_array_equal(rec["t"][i, :k], ref["rec_t"][i, :k])
+    return rec, ref
+
+
+@pytest.mark.parametrize("mode", ["FP64", "FP32", "MIX_F16_SR", "UNI_BF16_SR_NORM"])
+def test_event_record_matches_oracle(gpu, orc, mode):
+    # gene switches of the telegraph model (reactions 0 and 1), as for the
+    # dwell-time distributions; a capacity below some trajectories' counts
+    spec = wl.telegraph(0.05, 0.05, 20.0, 1.0)
+    x0 = np.array([1, 0, 0], np.int32)
+    rec, ref = run_records(gpu, orc, spec, x0, 300, 200.0, wl.snapshot_grid(200.0, 11), mode, 0b11, 12, seed=4)
+    assert (ref["rec_n"] > 12).any() and (ref["rec_n"] < 12).any()
+
+
+def test_event_record_chunked_and_every_reaction(gpu, orc):
+    # all reactions recorded (the log replays the trajectory) across snapshot
+    # windows: the count is carried between launches
+    spec = wl.telegraph(0.05, 0.05, 20.0, 1.0)
+    x0 = np.array([1, 0, 0], np.int32)
+    for chunks, window in ((1, 0), (3, 0), (2, 2)):
+        run_records(gpu, orc, spec, x0, 130, 20.0, wl.snapshot_grid(20.0, 9), "MIX_F16_SR", 0b1111, 1200,
+                    seed=2, n_chunks=chunks, first_window=window)
+
+
+def test_event_record_in_a_batch(gpu, orc):
+    # one item records, the other does not; both match the oracle
+    tele, bd = wl.telegraph(0.05, 0.05, 20.0, 1.0), wl.birth_death(20.0, 1.0)
+    items = [{"model": gpu.Model(tele), "x0": np.array([1, 0, 0], np.int32), "n_traj": 150, "record": (0b11, 20)},
+             {"model": gpu.Model(bd), "x0": np.array([0], np.int32), "n_traj": 100}]
+    print("[gpu-parity] records in a two-item batch", flush=True)
+    run = gpu.ssa_ensemble_run(items, 50.0, [25.0, 50.0], 8, "FP64")
+    ref = orc.simulate(tele, "FP64", items[0]["x0"], 50.0, [25.0, 50.0], 8, n_traj=150, record_mask=0b11,
+                       record_cap=20, threads=ORACLE_THREADS)
+    rec = run.records(0)
+    np.testing.assert_array_equal(rec["n"], ref["rec_n"])
+    k = np.minimum(ref["rec_n"], 20)
+    for i in range(150):
+        np.testing.assert_array_equal(rec["t"][i, :k[i]], ref["rec_t"][i, :k[i]])
+    ref_bd = orc.simulate(bd, "FP64", items[1]["x0"], 50.0, [25.0, 50.0], 8, n_traj=100, traj_id_base=150,
+                          threads=ORACLE_THREADS)
+    np.testing.assert_array_equal(run.snapshots(1), ref_bd["snap"])
+    with pytest.raises(gpu.SsaError):
+        run.records(1)
+
+
 def test_self_repressor_activation_and_repression(gpu, orc):
     spec = wl._build("hill_pair", ["X", "Y"], [
         {"change": {"X": +1}, "hill": ("repress", "Y", 1.0, 40.0, 15.0, 3)},

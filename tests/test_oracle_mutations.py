@@ -163,8 +163,8 @@ MUTATIONS = [
     ("mass action without 1/o!", "    return k / (double)d;", "    return k;", closed_dimer_law_fails),
     ("falling factorial offset dropped", "                        acc = acc * (double)(x[s] - i);",
      "                        acc = acc * (double)(x[s]);", closed_dimer_law_fails),
-    ("net change of the wrong reaction", "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[mu * N + s];\n        t = t_new;\n        ++n;\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    *n_out = n;\n    *t_out = t;",
-     "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[((mu + 1) % M) * N + s];\n        t = t_new;\n        ++n;\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    *n_out = n;\n    *t_out = t;",
+    ("net change of the wrong reaction", "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[mu * N + s];\n        t = t_new;\n        ++n;\n        record(o, &rec_cnt, mu, (double)t);\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    finish_record(o, rec_cnt);\n    *n_out = n;\n    *t_out = t;",
+     "        for (int s = 0; s < N; ++s)\n            x[s] += md->nu[((mu + 1) % M) * N + s];\n        t = t_new;\n        ++n;\n        record(o, &rec_cnt, mu, (double)t);\n        if (run->max_events && n == run->max_events) { status = ST_CAPPED; break; }\n    }\n    for (; k < K; ++k)\n        write_snap(o, k, N, x);\n    finish_record(o, rec_cnt);\n    *n_out = n;\n    *t_out = t;",
      birth_death_law_fails),
     ("waiting time with a wrong rate", "        double tau = or_nlog64(u1) / a0;", "        double tau = or_nlog64(u1) / (a0 + a[0]);",
      birth_death_law_fails),
