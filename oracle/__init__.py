@@ -90,6 +90,9 @@ def _open(path):
     for name in ("or_philox_batch", "or_nlog64_batch", "or_nlog32_batch", "or_uniform_batch"):
         getattr(lib, name).restype = None
     lib.or_round16_batch.restype = None
+    lib.or_sr_field_batch.restype = None
+    lib.or_sr_field_batch.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
     lib.or_round16_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int64]
     return lib
@@ -191,6 +194,20 @@ def simulate(model, mode: str, x0, t_end: float, snap_t, seed: int, *, n_traj: i
                          int(threads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
+    return out
+
+
+def sr_fields(fmt: str, seed: int, ids, ns, slots, conv, lib=None):
+    """The SR random halfwords (field << (16 - B)) the 16-bit trajectory code
+    reads for main (conv = 0) or conversion (conv = 1) slots; fmt 'F16' or 'BF16'."""
+    lib = lib or _load()
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    ns = np.ascontiguousarray(ns, dtype=np.uint64)
+    sl = np.ascontiguousarray(slots, dtype=np.int32)
+    cv = np.ascontiguousarray(conv, dtype=np.int32)
+    out = np.empty(ids.size, dtype=np.int32)
+    lib.or_sr_field_batch(ctypes.c_int(2 if fmt == "F16" else 3), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                          _ptr(ids), _ptr(ns), _ptr(sl), _ptr(cv), _ptr(out), ctypes.c_int64(ids.size))
     return out
 
 

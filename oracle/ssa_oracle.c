@@ -301,18 +301,28 @@ static int64_t factorial(int n)
 }
 
 /* Number of rounding slots each reaction's propensity uses (static schedule). */
-static int reaction_ops(const or_model *md, int j)
+/* Rounding ops of reaction j's propensity: count conversions (conversion    */
+/* slots) and the other ops (main slots).                                     */
+static int reaction_conv_ops(const or_model *md, int j)
 {
     const int N = md->n_species;
     if (md->law[j] == LAW_MASS_ACTION) {
         int total = 0;
         for (int s = 0; s < N; ++s)
             total += md->order[j * N + s];
-        return 2 * total;  /* one conversion + one multiply per factor */
+        return total;      /* one conversion per factor */
     }
+    return 1;              /* the regulator's count */
+}
+
+static int reaction_main_ops(const or_model *md, int j)
+{
+    if (md->law[j] == LAW_MASS_ACTION)
+        return reaction_conv_ops(md, j);   /* one multiply per factor */
+    /* q = x/K, h-1 powers, d = 1 + q^h, f = v/d (activation: g = v q^h, f = g/d), a = b + f */
     if (md->law[j] == LAW_HILL_REPRESS)
-        return md->hill_h[j] + 4;
-    return md->hill_h[j] + 5;
+        return md->hill_h[j] + 3;
+    return md->hill_h[j] + 4;
 }
 
 static void record(const or_out *o, uint32_t *cnt, int mu, double t)
@@ -560,40 +570,81 @@ static void traj_fp32(const or_model *md, const or_run *run, int64_t idx, const 
 /* its static slot.                                                           */
 /*                                                                            */
 /* Slot schedule per event (slot numbers are fixed by the model, so skipped   */
-/* ops leave their slots unused):                                            */
-/*   propensities: reaction by reaction, op by op  [0, P)                     */
-/*   uniform mode, in order: M normalisations (if norm), M-1 partial sums,    */
-/*     -ln(u1), tau, tau/m (if norm), t + tau, u2 * a0.                      */
+/* ops leave their slots unused). Two kinds of slots:                        */
+/*   main slots - propensity ops other than count conversions, reaction by   */
+/*     reaction, op by op [0, P); then, uniform mode, in order: M            */
+/*     normalisations (if norm), M-1 partial sums, -ln(u1), tau, tau/m (if   */
+/*     norm), t + tau, u2 * a0;                                              */
+/*   conversion slots - the int -> 16-bit conversions of counts, in the same */
+/*     op order [0, C).                                                      */
 /* With SR only at accumulation points (the paper's "selective SR", Sec. 3.3  */
-/* last paragraph) the partial sums take slots 0..M-2 and the clock update    */
-/* slot M-1; every other op rounds to nearest and takes no slot.              */
-/* Halfword of slot s: slots 0..3 are words 2,3 of the event's stream-0 draw  */
-/* (low half first); slot 4 + 8q + r is half r%2 of word r/2 of the stream    */
-/* q+1 draw.                                                                  */
+/* last paragraph) the partial sums take main slots 0..M-2 and the clock      */
+/* update slot M-1; every other op rounds to nearest and takes no slot.       */
+/*                                                                            */
+/* Random field of a slot (Sec. 3.3: SR to fp16 discards 13 mantissa bits of  */
+/* a binary32 result, to bf16 16, and needs that many random bits; B = 13 or  */
+/* 16). A string of bits is cut into B-bit fields from its low end: field r   */
+/* is bits [rB, rB + B), bit 0 being bit 0 of the string's first word, and    */
+/* fields may span two words. Main slots: the first F0 = floor(80/B) are the  */
+/* fields of the 80-bit string (word 2, word 3, then the low bytes of words 0 */
+/* and 1) of the event's stream-0 draw, whose words 0 and 1 give the two      */
+/* 24-bit uniforms from their high bits; main slot F0 + F1 q + r is field r   */
+/* of the 128-bit string of the stream-(q+1) draw (F1 = floor(128/B)).        */
+/* Conversion slot F1 q + r is field r of the stream-(2^31 + q) draw. A       */
+/* conversion's bits matter only when the count is not exactly representable */
+/* (|count| > 2^11 fp16, 2^8 bf16). The field f is passed to or_round16 as   */
+/* the halfword f << (16 - B).                                               */
 /* ------------------------------------------------------------------------- */
+#define SR_CONV_STREAM 0x80000000u
+
 typedef struct {
     uint64_t seed;
     uint32_t id;
     uint64_t n;
+    int B;             /* field width */
     uint32_t w0[4];
-    int have;          /* highest extra stream drawn so far */
+    int have;          /* main extra streams drawn so far */
     uint32_t ws[64][4];
+    int have_cv;       /* conversion streams drawn so far */
+    uint32_t wc[64][4];
 } sr_ctx;
+
+/* bits [off, off + B) of a little-endian string of 32-bit words */
+static uint32_t bit_field(const uint32_t *w, int off, int B)
+{
+    uint64_t pair = (uint64_t)w[off / 32];
+    if (off % 32 + B > 32)
+        pair |= (uint64_t)w[off / 32 + 1] << 32;
+    return (uint32_t)((pair >> (off % 32)) & ((1u << B) - 1u));
+}
 
 static int sr_bits(sr_ctx *c, int slot)
 {
-    uint32_t word;
-    if (slot < 4) {
-        word = c->w0[2 + slot / 2];
-        return (int)((slot % 2) ? (word >> 16) : (word & 0xFFFFu));
+    const int B = c->B, F0 = 80 / B, F1 = 128 / B;
+    uint32_t f;
+    if (slot < F0) {
+        uint32_t s0[3] = {c->w0[2], c->w0[3], (c->w0[0] & 0xFFu) | ((c->w0[1] & 0xFFu) << 8)};
+        f = bit_field(s0, slot * B, B);
+    } else {
+        int q = (slot - F0) / F1, r = (slot - F0) % F1;
+        while (c->have <= q) {
+            draw(c->seed, c->id, c->n, (uint32_t)(c->have + 1), c->ws[c->have]);
+            c->have++;
+        }
+        f = bit_field(c->ws[q], r * B, B);
     }
-    int q = (slot - 4) / 8, r = (slot - 4) % 8;
-    while (c->have <= q) {
-        draw(c->seed, c->id, c->n, (uint32_t)(c->have + 1), c->ws[c->have]);
-        c->have++;
+    return (int)(f << (16 - B));
+}
+
+static int sr_conv_bits(sr_ctx *c, int slot)
+{
+    const int B = c->B, F1 = 128 / B;
+    int q = slot / F1, r = slot % F1;
+    while (c->have_cv <= q) {
+        draw(c->seed, c->id, c->n, SR_CONV_STREAM + (uint32_t)c->have_cv, c->wc[c->have_cv]);
+        c->have_cv++;
     }
-    word = c->ws[q][r / 2];
-    return (int)((r % 2) ? (word >> 16) : (word & 0xFFFFu));
+    return (int)(bit_field(c->wc[q], r * B, B) << (16 - B));
 }
 
 typedef struct {
@@ -602,10 +653,17 @@ typedef struct {
     sr_ctx *ctx;
 } rounder;
 
-/* Round the float result of one op; 'slot' is that op's static slot. */
+/* Round the float result of one op; 'slot' is that op's static main slot. */
 static float rnd(const rounder *R, float v, int slot)
 {
     int rb = R->sr ? sr_bits(R->ctx, slot) : -1;
+    return (float)or_round16(R->fmt, (double)v, rb);
+}
+
+/* Round a converted count; 'slot' is its conversion slot. */
+static float rnd_conv(const rounder *R, float v, int slot)
+{
+    int rb = R->sr ? sr_conv_bits(R->ctx, slot) : -1;
     return (float)or_round16(R->fmt, (double)v, rb);
 }
 
@@ -618,8 +676,8 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
     const int selective = mode.sr == 2;
     int32_t x[MAXN];
     float c[MAXM], hb[MAXM], hK[MAXM];
-    int base[MAXM];
-    int P = 0;
+    int base[MAXM], cbase[MAXM];
+    int P = 0, C = 0;
     for (int s = 0; s < N; ++s)
         x[s] = run->x0[s];
     for (int j = 0; j < M; ++j) {
@@ -630,7 +688,9 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
         hb[j] = (float)or_round16(mode.fmt, md->hill_b ? md->hill_b[j] : 0.0, -1);
         hK[j] = (float)or_round16(mode.fmt, md->hill_K ? md->hill_K[j] : 1.0, -1);
         base[j] = P;
-        P += reaction_ops(md, j);
+        P += reaction_main_ops(md, j);
+        cbase[j] = C;
+        C += reaction_conv_ops(md, j);
     }
     /* accumulation-phase slots (uniform mode) */
     const int slot_norm = P;
@@ -655,13 +715,15 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
         ctx.id = id;
         ctx.n = n;
         ctx.have = 0;
+        ctx.have_cv = 0;
+        ctx.B = mode.fmt == OR_FP16 ? 13 : 16;
         draw(run->seed, id, n, 0, ctx.w0);
         float u1 = or_u24(ctx.w0[0]);
         float u2 = or_u24(ctx.w0[1]);
         float a[MAXM], S[MAXM];
         double Sd[MAXM], ad[MAXM];
         for (int j = 0; j < M; ++j) {
-            int sl = base[j];
+            int sl = base[j], cs = cbase[j];
             if (md->law[j] == LAW_MASS_ACTION) {
                 int zero = 0;
                 for (int s = 0; s < N; ++s)
@@ -674,12 +736,12 @@ static void traj_16(const or_model *md, or_mode mode, const or_run *run, int64_t
                 float acc = c[j];
                 for (int s = 0; s < N; ++s)
                     for (int i = 0; i < md->order[j * N + s]; ++i) {
-                        float fv = rnd(&R, (float)(x[s] - i), sl++);
+                        float fv = rnd_conv(&R, (float)(x[s] - i), cs++);
                         acc = rnd(&R, acc * fv, sl++);
                     }
                 a[j] = acc;
             } else {
-                float xr = rnd(&R, (float)x[md->hill_reg[j]], sl++);
+                float xr = rnd_conv(&R, (float)x[md->hill_reg[j]], cs++);
                 float q = rnd(&R, xr / hK[j], sl++);
                 float qh = q;
                 for (int i = 1; i < md->hill_h[j]; ++i)
@@ -775,6 +837,17 @@ int or_simulate(const or_model *md, or_mode mode, const or_run *run, const int64
         return -1;
     if (rec && (rec->cap < 0 || (rec->cap > 0 && (!rec->t || !rec->j)) || !rec->n))
         return -1;
+    if (mode.fmt >= OR_FP16) {
+        /* the random-field streams an event may draw must fit sr_ctx */
+        int P = 0, C = 0, M = md->n_reactions;
+        for (int j = 0; j < M; ++j) {
+            P += reaction_main_ops(md, j);
+            C += reaction_conv_ops(md, j);
+        }
+        const int B = mode.fmt == OR_FP16 ? 13 : 16;
+        if (P + 2 * M + 4 > 80 / B + 64 * (128 / B) || C > 64 * (128 / B))
+            return -1;
+    }
     if (n_threads < 1)
         n_threads = 1;
     int64_t i;
@@ -794,6 +867,25 @@ int or_simulate(const or_model *md, or_mode mode, const or_run *run, const int64
 /* ------------------------------------------------------------------------- */
 /* Vectorised numerics entry points used by the pin tests.                    */
 /* ------------------------------------------------------------------------- */
+/* SR random fields as the trajectory code reads them: for each i, the       */
+/* halfword (field << (16 - B)) of main slot (conv[i] == 0) or conversion    */
+/* slot (conv[i] != 0) slot[i] of event n[i] of trajectory id[i].            */
+void or_sr_field_batch(int fmt, uint64_t seed, const uint32_t *id, const uint64_t *n, const int32_t *slot,
+                       const int32_t *conv, int32_t *out, int64_t count)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        sr_ctx c;
+        c.seed = seed;
+        c.id = id[i];
+        c.n = n[i];
+        c.B = fmt == OR_FP16 ? 13 : 16;
+        c.have = 0;
+        c.have_cv = 0;
+        draw(seed, id[i], n[i], 0, c.w0);
+        out[i] = conv[i] ? sr_conv_bits(&c, slot[i]) : sr_bits(&c, slot[i]);
+    }
+}
+
 void or_philox_batch(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i)

@@ -129,31 +129,43 @@ int mass_action_total_order(const Model &md, int j)
     return t;
 }
 
-int reaction_slots(const Model &md, int j)
+// Rounding ops of reaction j: count conversions (conversion slots) and the
+// other ops (main slots): mass action one of each per factor; Hill one
+// conversion and q = x/K, h-1 powers, 1 + q^h, v/d (activation also v q^h),
+// b + f.
+int reaction_conv_slots(const Model &md, int j)
+{
+    return md.law[j].kind == SSA_LAW_MASS_ACTION ? mass_action_total_order(md, j) : 1;
+}
+
+int reaction_main_slots(const Model &md, int j)
 {
     const ssa_law &L = md.law[j];
     if (L.kind == SSA_LAW_MASS_ACTION)
-        return 2 * mass_action_total_order(md, j);
-    return L.h + (L.kind == SSA_LAW_HILL_REPRESS ? 4 : 5);
+        return mass_action_total_order(md, j);
+    return L.h + (L.kind == SSA_LAW_HILL_REPRESS ? 3 : 4);
 }
 
 // Device description of one network: propensity op sequence with its static
-// rounding slots, and the integer update x += nu_mu.
+// rounding slots (main and conversion), and the integer update x += nu_mu.
 std::string gen_model(const Model &md, int idx, uint64_t record_mask)
 {
-    int nprop = 0;
-    for (int j = 0; j < md.M; ++j)
-        nprop += reaction_slots(md, j);
+    int nprop = 0, nconv = 0;
+    for (int j = 0; j < md.M; ++j) {
+        nprop += reaction_main_slots(md, j);
+        nconv += reaction_conv_slots(md, j);
+    }
     std::ostringstream o;
     o << "struct Md" << idx << " {\n"
-      << "  static constexpr int N = " << md.N << ", M = " << md.M << ", NPROP = " << nprop << ";\n"
+      << "  static constexpr int N = " << md.N << ", M = " << md.M << ", NPROP = " << nprop << ", NCONV = " << nconv
+      << ";\n"
       << "  static constexpr u64 REC = " << record_mask << "ull;  // reactions whose firings are recorded\n"
-      << "  template <class P, class PoolT>\n"
+      << "  template <class P, bool EXACT, class PoolT, class CPoolT>\n"
       << "  __device__ static __forceinline__ void propensities(const i32 (&x)[N], const typename P::T (&c)[M],"
-      << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool) {\n"
+      << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool, const CPoolT &cpool) {\n"
       << "    typedef typename P::T T;\n"
-      << "    (void)hill; (void)pool;\n";
-    int slot = 0;
+      << "    (void)hill; (void)pool; (void)cpool;\n";
+    int slot = 0, cslot = 0;
     for (int j = 0; j < md.M; ++j) {
         const ssa_law &L = md.law[j];
         if (L.kind == SSA_LAW_MASS_ACTION) {
@@ -166,9 +178,10 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
             for (int s = 0; s < md.N; ++s) {
                 int os = md.order[(size_t)j * md.N + s];
                 for (int i = 0; i < os; ++i) {
-                    o << "      acc = P::mul(acc, P::cvt(x[" << s << "] - " << i << ", pool.hw(" << slot
-                      << ")), pool.hw(" << slot + 1 << "));\n";
-                    slot += 2;
+                    o << "      acc = P::mul(acc, P::template cvt<EXACT>(x[" << s << "] - " << i << ", cpool.hw("
+                      << cslot << ")), pool.hw(" << slot << "));\n";
+                    slot += 1;
+                    cslot += 1;
                 }
                 if (os > 0) {
                     if (!zero.empty())
@@ -179,10 +192,10 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
             o << "      a[" << j << "] = (" << zero << ") ? (T)0 : acc; }\n";
         } else {
             int b = slot;
-            o << "    { T xr = P::cvt(x[" << L.regulator << "], pool.hw(" << b << "));\n"
-              << "      T q = P::div(xr, hill[" << 2 * j + 1 << "], pool.hw(" << b + 1 << "));\n"
+            o << "    { T xr = P::template cvt<EXACT>(x[" << L.regulator << "], cpool.hw(" << cslot++ << "));\n"
+              << "      T q = P::div(xr, hill[" << 2 * j + 1 << "], pool.hw(" << b << "));\n"
               << "      T qh = q;\n";
-            int sl = b + 2;
+            int sl = b + 1;
             for (int i = 1; i < L.h; ++i)
                 o << "      qh = P::mul(qh, q, pool.hw(" << sl++ << "));\n";
             o << "      T d = P::add((T)1, qh, pool.hw(" << sl++ << "));\n";

@@ -20,10 +20,15 @@
 //
 // Random bits: Philox4x32-10, key = seed, counter = (event lo, event hi,
 // trajectory id, stream). Stream 0 gives the two uniforms (53-bit pairs in
-// FP64, 24-bit words otherwise) and, in SR modes, rounding halfwords 0..3;
-// stream q supplies halfwords 4+8(q-1) .. 11+8(q-1). Every rounding op of an
-// event owns a fixed halfword slot, so a step's randomness is a function of
-// (seed, trajectory, event) only and results do not depend on lane scheduling.
+// FP64, the high 24 bits of words 0 and 1 otherwise). In SR modes every
+// rounding op of an event owns a fixed slot holding a B-bit random field
+// (B = 13 for fp16, 16 for bf16: the mantissa bits a binary32 -> 16-bit
+// rounding discards). Main slots are fields of the 80 spare bits of stream 0,
+// then of streams 1, 2, ...; conversions of counts have their own slots in
+// streams 2^31, 2^31 + 1, ..., drawn only when a count is not exactly
+// representable (otherwise the conversion rounds nothing). A step's randomness
+// is a function of (seed, trajectory, event) only, so results do not depend on
+// lane scheduling.
 #pragma clang fp contract(off)
 
 typedef unsigned int u32;
@@ -207,6 +212,9 @@ struct PrecF64 {
     typedef double A;
     typedef double Tm;
     static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true, SELECTIVE = false;
+    static constexpr i32 EXACT_INT = 0;   // conversions are exact: no count test
+    static constexpr int SR_B = 16;
+    template <bool EXACT>
     __device__ static T cvt(i32 v, u32) { return (double)v; }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
@@ -222,6 +230,9 @@ struct PrecF32 {
     typedef float A;
     typedef float Tm;
     static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false, SELECTIVE = false;
+    static constexpr i32 EXACT_INT = 0;
+    static constexpr int SR_B = 16;
+    template <bool EXACT>
     __device__ static T cvt(i32 v, u32) { return (float)v; }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
@@ -274,7 +285,18 @@ struct Prec16 {
     typedef float Tm;
     static constexpr bool SR = RND != 0, UNI = UNIF, NORM = NRM, WIDE = false, SELECTIVE = RND == 2;
     static constexpr bool SR_OPS = RND == 1, SR_ACC = RND != 0;
-    __device__ static T cvt(i32 v, u32 rb) { return rnd16<FMT, SR_OPS>((float)v, rb); }
+    static constexpr int SR_B = FMT == FMT_FP16 ? 13 : 16;   // random bits per SR rounding
+    // counts up to EXACT_INT in magnitude are 16-bit values already: their
+    // conversion rounds nothing (by either rule) and needs no random bits
+    static constexpr i32 EXACT_INT = FMT == FMT_FP16 ? 2048 : 256;
+    template <bool EXACT>
+    __device__ static T cvt(i32 v, u32 rb)
+    {
+        if constexpr (EXACT)
+            return (float)v;
+        else
+            return rnd16<FMT, SR_OPS>((float)v, rb);
+    }
     __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(mul32<FMT>(a, b), rb); }
     __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a / b, rb); }
     __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(add32<FMT>(a, b), rb); }
@@ -297,24 +319,76 @@ struct Prec16 {
 };
 
 // --------------------------------------------------------------------------
-// Rounding-halfword pool of one event: words 2, 3 of the stream-0 draw, then
-// four words from each further stream. Slot s is half (s & 1) of word s >> 1
-// (half 0 = bits 15..0). hw(s) is the SR conversions' random operand for slot
-// s: the halfword in bits 31..16 (an odd slot's word as it is, since the
-// conversions ignore bits 15..0).
+// Random fields of one event. A string of bits is cut into B-bit fields from
+// its low end (field r = bits [rB, rB + B), spanning two words when it must).
+// Pool (main slots): the 80-bit string w[0..2] = (stream-0 word 2, word 3,
+// low bytes of words 0 and 1) holds F0 = floor(80/B) fields; each further
+// stream's 128-bit string (4 words) holds F1 = floor(128/B). ConvPool
+// (conversion slots): F1 fields per stream 2^31 + q. hw(s) is the SR
+// conversions' random operand for slot s: the field in bits 31..32-B (the
+// instructions read only those; the bits below are don't-cares). Slot numbers
+// are compile-time constants, so each hw is one shift or one funnel shift.
 // --------------------------------------------------------------------------
-template <int NSLOT>
+template <int B>
+__device__ __forceinline__ u32 field_operand(const u32 *w, int off)
+{
+    const int wi = off / 32, p = off % 32;
+    if (p + B <= 32)
+        return w[wi] << (32 - B - p);
+    return __builtin_amdgcn_alignbit(w[wi + 1], w[wi], p + B - 32);
+}
+
+template <int NSLOT, int B>
 struct Pool {
-    static constexpr int NSTREAM = NSLOT <= 4 ? 1 : 1 + (NSLOT - 4 + 7) / 8;
-    static constexpr int NW = NSLOT <= 0 ? 1 : 2 + 4 * (NSTREAM - 1);
+    static constexpr int F0 = 80 / B, F1 = 128 / B;
+    static constexpr int NSTREAM = NSLOT <= F0 ? 1 : 1 + (NSLOT - F0 + F1 - 1) / F1;
+    static constexpr int NW = NSLOT <= 0 ? 1 : 3 + 4 * (NSTREAM - 1);
     u32 w[NW];
     // slots past the pool belong to ops that do not round stochastically
     __device__ __forceinline__ u32 hw(int s) const
     {
-        if (s >= 2 * NW)
+        if (s >= NSLOT)
             return 0u;
-        return (s & 1) ? w[s >> 1] : (w[s >> 1] << 16);
+        if (s < F0)
+            return field_operand<B>(w, s * B);
+        return field_operand<B>(w + 3 + 4 * ((s - F0) / F1), ((s - F0) % F1) * B);
     }
+};
+
+#define SSA_CONV_STREAM 0x80000000u
+
+template <int NCONV, int B>
+struct ConvPool {
+    static constexpr int F1 = 128 / B;
+    static constexpr int NSTREAM = NCONV <= 0 ? 0 : (NCONV + F1 - 1) / F1;
+    u32 w[NSTREAM > 0 ? 4 * NSTREAM : 1];
+    __device__ __forceinline__ u32 hw(int s) const
+    {
+        if (s >= NCONV)
+            return 0u;
+        return field_operand<B>(w + 4 * (s / F1), (s % F1) * B);
+    }
+};
+
+// Conversion fields of event n (drawn only when a count is not exactly representable).
+template <int NCONV, int B>
+__device__ __forceinline__ ConvPool<NCONV, B> make_conv(u64 n, u32 id, u32 k0, u32 k1)
+{
+    ConvPool<NCONV, B> cp;
+#pragma unroll
+    for (int q = 0; q < ConvPool<NCONV, B>::NSTREAM; ++q) {
+        W4 r = philox10((u32)n, (u32)(n >> 32), id, SSA_CONV_STREAM + (u32)q, k0, k1);
+        cp.w[4 * q + 0] = r.w0;
+        cp.w[4 * q + 1] = r.w1;
+        cp.w[4 * q + 2] = r.w2;
+        cp.w[4 * q + 3] = r.w3;
+    }
+    return cp;
+}
+
+// A conversion pool for runs whose conversions need no random bits.
+struct NoConv {
+    __device__ __forceinline__ u32 hw(int) const { return 0u; }
 };
 
 // --------------------------------------------------------------------------
@@ -325,7 +399,7 @@ struct Pool {
 // --------------------------------------------------------------------------
 template <class P, int NSLOT>
 struct Draw {
-    Pool<NSLOT> pool;
+    Pool<NSLOT, P::SR_B> pool;
     typename P::A L;
     typename P::A u2;
 };
@@ -338,13 +412,14 @@ __device__ __forceinline__ Draw<P, NSLOT> make_draw(u64 n, u32 id, u32 k0, u32 k
     if constexpr (NSLOT > 0) {
         d.pool.w[0] = r0.w2;
         d.pool.w[1] = r0.w3;
+        d.pool.w[2] = (r0.w0 & 0xFFu) | ((r0.w1 & 0xFFu) << 8);
 #pragma unroll
-        for (int q = 1; q < Pool<NSLOT>::NSTREAM; ++q) {
+        for (int q = 1; q < Pool<NSLOT, P::SR_B>::NSTREAM; ++q) {
             W4 rq = philox10((u32)n, (u32)(n >> 32), id, (u32)q, k0, k1);
-            d.pool.w[2 + 4 * (q - 1) + 0] = rq.w0;
-            d.pool.w[2 + 4 * (q - 1) + 1] = rq.w1;
-            d.pool.w[2 + 4 * (q - 1) + 2] = rq.w2;
-            d.pool.w[2 + 4 * (q - 1) + 3] = rq.w3;
+            d.pool.w[3 + 4 * (q - 1) + 0] = rq.w0;
+            d.pool.w[3 + 4 * (q - 1) + 1] = rq.w1;
+            d.pool.w[3 + 4 * (q - 1) + 2] = rq.w2;
+            d.pool.w[3 + 4 * (q - 1) + 3] = rq.w3;
         }
     }
     if constexpr (P::WIDE) {
@@ -545,10 +620,30 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
                 const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
-                const Pool<NSLOT> &pool = cur.pool;
-                // ---- propensities (generated op sequence)
+                const Pool<NSLOT, P::SR_B> &pool = cur.pool;
+                // ---- propensities (generated op sequence). Conversions of
+                // counts draw random bits only when they round: when every
+                // count of every lane is exactly representable in the 16-bit
+                // type the exact version runs and no conversion stream is drawn.
                 T a[M];
-                Md::template propensities<P>(x, c, hill, a, pool);
+                if constexpr (P::SR && !P::SELECTIVE && Md::NCONV > 0) {
+                    i32 mx = x[0] < 0 ? -x[0] : x[0];
+#pragma unroll
+                    for (int s = 1; s < N; ++s)
+                        mx = (x[s] < 0 ? -x[s] : x[s]) > mx ? (x[s] < 0 ? -x[s] : x[s]) : mx;
+                    if (__builtin_expect(__ballot(mx > P::EXACT_INT) == 0, 1)) {
+                        Md::template propensities<P, true>(x, c, hill, a, pool, NoConv());
+                    } else {
+                        // the empty asm keeps this a branch: merged with the exact
+                        // version, the conversion stream would be drawn every event
+                        __asm__ volatile("");
+                        const ConvPool<Md::NCONV, P::SR_B> cpool =
+                            make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
+                        Md::template propensities<P, false>(x, c, hill, a, pool, cpool);
+                    }
+                } else {
+                    Md::template propensities<P, false>(x, c, hill, a, pool, NoConv());
+                }
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
                 bool m_ok = true;

@@ -166,16 +166,46 @@ def _slots(block):
     return sum(weight(op) for _, op, _ in block if op.startswith("v_"))
 
 
+def _lightest_cycle(blocks, succ, body, B):
+    """Cycle from B back to B inside `body` with the fewest VALU slots
+    (Dijkstra with block weights; edges into B end at a sink)."""
+    import heapq
+    best = {B: _slots(blocks[B])}
+    prev = {}
+    heap = [(best[B], B)]
+    while heap:
+        c, n = heapq.heappop(heap)
+        if c > best.get(n, float("inf")):
+            continue
+        if n == -1:
+            path, m = [], prev[-1]
+            while m != B:
+                path.append(m)
+                m = prev[m]
+            path.append(B)
+            return c, sorted(path)
+        for t in succ[n]:
+            if t not in body:
+                continue
+            nxt, nc = (-1, c) if t == B else (t, c + _slots(blocks[t]))
+            if nc < best.get(nxt, float("inf")):
+                best[nxt] = nc
+                prev[nxt] = n
+                heapq.heappush(heap, (nc, nxt))
+    return None
+
+
 def event_paths(co_path: str):
     """Lightest event of each copy of the event loop (the compiler may
-    unswitch it). For an innermost loop holding the next event's Philox calls,
-    B is its block with the most Philox multiplies; the event is the cycle from
-    B back to B with the fewest VALU slots (a shortest path with block
-    weights). Rare blocks (snapshot stores, trajectory completion, the
-    selection fallback, refills) are off that cycle, and where a wave-uniform
-    test picks one of two versions of a step, the lighter is counted, so the
-    work derived from it is never overstated."""
-    import heapq
+    unswitch it). Every iteration of an innermost loop holding the Philox calls
+    passes through the block with the next event's draw, so one event is the
+    lightest cycle through some block holding Philox multiplies: the minimum,
+    over those blocks, of the cycle through the block with the fewest VALU
+    slots. Rare blocks (snapshot stores, status resolution, completion, the
+    selection fallback, refills, extra random streams drawn only in rare
+    cases) are off that cycle, and where a wave-uniform test picks one of two
+    versions of a step, the lighter is counted, so the work derived from it is
+    never overstated."""
     insts = disassemble(co_path)
     blocks, order, succ = build_cfg(insts)
     dom = dominators(order, succ, order[0])
@@ -189,35 +219,10 @@ def event_paths(co_path: str):
     inner = {h: body for h, body in cands.items() if not any(h2 != h and h2 in body for h2 in cands)}
     paths = []
     for h, body in inner.items():
-        B = max(sorted(body), key=lambda b: sum(1 for _, op, _ in blocks[b] if _is_mul(op)))
-        # Dijkstra over blocks; cost of a path = slots of the blocks it enters
-        best = {B: _slots(blocks[B])}
-        prev = {}
-        heap = [(best[B], B)]
-        done = None
-        while heap:
-            c, n = heapq.heappop(heap)
-            if c > best.get(n, float("inf")):
-                continue
-            if n == -1:
-                done = c
-                break
-            for t in succ[n]:
-                if t not in body:
-                    continue
-                nxt, nc = (-1, c) if t == B else (t, c + _slots(blocks[t]))
-                if nc < best.get(nxt, float("inf")):
-                    best[nxt] = nc
-                    prev[nxt] = n
-                    heapq.heappush(heap, (nc, nxt))
-        if done is None:
-            continue
-        path, n = [], prev[-1]
-        while n != B:
-            path.append(n)
-            n = prev[n]
-        path.append(B)
-        paths.append(sorted(path))
+        cycles = [_lightest_cycle(blocks, succ, body, b) for b in sorted(body) if n_mul([b]) >= 8]
+        cycles = [cy for cy in cycles if cy is not None]
+        if cycles:
+            paths.append(min(cycles)[1])
     if not paths:
         raise RuntimeError("no event loop found in " + co_path)
     return blocks, paths

@@ -2,8 +2,10 @@
 // relies on, run against the kernel's own device functions (the template is
 // included as it is).
 //
-//  * The SR conversions read only bits 31..16 of their random operand, so an
-//    odd rounding slot may pass its Philox word unmasked.
+//  * The SR conversions read only the top B bits of their random operand
+//    (B = 13 for fp16: bits 31..19; B = 16 for bf16: bits 31..16), so a
+//    B-bit random field shifted to the top may carry the neighbouring
+//    fields below it.
 //  * div_rn_inrange (the short fma division) returns the IEEE quotient for
 //    every log argument and for -ln(u1) / a0 over the fp16 ranges.
 //
@@ -35,7 +37,7 @@ __global__ void check_sr_lowbits(unsigned long long n, unsigned long long *cnt)
         // magnitudes 2^-37 .. 2^33: fp16 subnormals, normals and overflow, bf16 normals
         vb = (vb & 0x807FFFFFu) | ((90u + (vb >> 23) % 71u) << 23);
         const float v = __uint_as_float(vb);
-        if (__float_as_uint(sr_f16(v, w)) != __float_as_uint(sr_f16(v, w & 0xFFFF0000u)))
+        if (__float_as_uint(sr_f16(v, w)) != __float_as_uint(sr_f16(v, w & 0xFFF80000u)))
             atomicAdd(&cnt[0], 1ull);
         if (__float_as_uint(sr_bf16(v, w)) != __float_as_uint(sr_bf16(v, w & 0xFFFF0000u)))
             atomicAdd(&cnt[1], 1ull);
@@ -92,8 +94,8 @@ int alloc_counters(unsigned long long **d, int n)
 
 extern "C" {
 
-// Mismatches of the SR conversions with and without the operand's low half,
-// over n random (value, word) pairs: out[0] fp16, out[1] bf16.
+// Mismatches of the SR conversions with and without the operand's bits below
+// the top B, over n random (value, word) pairs: out[0] fp16, out[1] bf16.
 int gpu_check_sr_lowbits(unsigned long long n, unsigned long long *out)
 {
     unsigned long long *d = nullptr;

@@ -2,9 +2,10 @@
 against the kernel's own device functions (tests/gpu_checks.hip includes the
 device template):
 
-* gfx950's SR conversions read only bits 31..16 of their random operand, so
-  an odd rounding slot passes its Philox word unmasked (the rounding rule the
-  oracle states is then unchanged);
+* gfx950's SR conversions read only the top B bits of their random operand
+  (13 for fp16, 16 for bf16), so the kernel may hand a conversion a packed
+  word whose low bits belong to other random fields (the rounding rule the
+  oracle states, on the field alone, is then unchanged);
 * the short fma division (div_rn_inrange) returns the IEEE quotient on every
   log argument and on -ln(u1)/a0 over the fp16 ranges, so the kernel's
   waiting times equal the oracle's correctly rounded divisions.
@@ -29,7 +30,7 @@ def _lib():
 
 
 @pytest.mark.gpu
-def test_sr_conversions_ignore_low_half_of_random_operand():
+def test_sr_conversions_read_only_top_bits_of_random_operand():
     out = (ctypes.c_ulonglong * 2)()
     n = 1 << 26
     print(f"[gpu-facts] sr low bits, {n} pairs", flush=True)
