@@ -480,6 +480,15 @@ __device__ __forceinline__ u32 lane_id()
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
+// Mask of the wave's lanes where c holds. Given one comparison, the mask is the
+// comparison's own result; a conjunction is formed as the AND of its terms'
+// masks (scalar ops), since a mask of a combined condition costs two dependent
+// vector ops more.
+__device__ __forceinline__ u64 lanes(bool c)
+{
+    return __builtin_amdgcn_ballot_w64(c);
+}
+
 __device__ __forceinline__ u32 rank_in(u64 mask)
 {
     return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
@@ -523,14 +532,15 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
     const Tm t_end = P::WIDE ? (Tm)L.t_end64 : (Tm)L.t_end32;
     const u32 lane = lane_id();
 
-    i32 x[N];
-    T c[M];
+    // initialised: a lane without a trajectory still runs the event step on them
+    i32 x[N] = {};
+    T c[M] = {};
     Tm t = 0;
     u64 n = 0;
     i32 k = 0;
     Tm t_next = 0;     // time of snapshot k (infinity past the last row of this launch)
     Tm t_stop = 0;     // an event at t_new fires only if t_new <= t_stop (-infinity: suspend)
-    Draw<P, NSLOT> cur;
+    Draw<P, NSLOT> cur = {};
     u64 n_claim = 0;   // event index when this launch claimed the trajectory
     u32 rec_cnt = 0;   // recorded firings of this trajectory (Md::REC reactions)
     const u64 n_stop = L.max_events ? L.max_events : ~0ull;
@@ -607,16 +617,18 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     open = false;
             }
         }
-        u64 act = __ballot(active);
+        u64 act = lanes(active);   // the wave's lanes holding a trajectory
         if (act == 0) {
             if (!open)
                 break;
             continue;
         }
 
+        // Every lane runs the event step, also one without a trajectory: such a
+        // lane never fires, stores nothing and leaves its registers unused, and
+        // the step needs no exec-mask save and restore around it.
         for (;;) {
-            bool stopped = false;
-            if (active) {
+            {   // one event step
                 // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
                 const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
@@ -631,7 +643,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
 #pragma unroll
                     for (int s = 1; s < N; ++s)
                         mx = (x[s] < 0 ? -x[s] : x[s]) > mx ? (x[s] < 0 ? -x[s] : x[s]) : mx;
-                    if (__builtin_expect(__ballot(mx > P::EXACT_INT) == 0, 1)) {
+                    if (__builtin_expect((act & lanes(mx > P::EXACT_INT)) == 0, 1)) {
                         Md::template propensities<P, true>(x, c, hill, a, pool, NoConv());
                     } else {
                         // the empty asm keeps this a branch: merged with the exact
@@ -668,8 +680,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 const A a0 = S[M - 1];
                 // a0 in (0, largest finite]: false for zero, negatives, infinity and NaN
                 bool a_ok;
-                if constexpr (P::WIDE)
-                    a_ok = a0 > 0.0 && a0 <= 1.7976931348623157e308;
+                if constexpr (P::WIDE)   // positive finite binary64: bit patterns 1 .. 0x7FEFFFFFFFFFFFFF
+                    a_ok = (u64)__double_as_longlong(a0) - 1ull < 0x7FEFFFFFFFFFFFFFull;
                 else
                     a_ok = __float_as_uint(a0) - 1u < 0x7F7FFFFFu;
                 a_ok = a_ok && m_ok;
@@ -685,8 +697,9 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 }
                 // ---- snapshots strictly before t_new hold the current state (rare;
                 // the wave-uniform test lets the compiler place the stores out of line)
-                const bool snap_due = a_ok && t_next < t_new;
-                if (__builtin_expect(__ballot(snap_due) != 0, 0) && snap_due) {
+                const u64 ok_lanes = act & lanes(a_ok);
+                const bool snap_due = active && a_ok && t_next < t_new;
+                if (__builtin_expect((ok_lanes & lanes(t_next < t_new)) != 0, 0) && snap_due) {
                     do {
 #pragma unroll
                         for (int s = 0; s < N; ++s)
@@ -696,14 +709,15 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     } while (t_next < t_new);
                     t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
                 }
-                const bool fire = a_ok && t_new <= t_stop;
+                const bool fire = active && a_ok && t_new <= t_stop;
+                const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
                 // ---- selection: mu = number of prefix sums at or below the target
                 const A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
                 int mu = 0;
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     mu += (S[j] <= target) ? 1 : 0;
-                if (__builtin_expect(__ballot(mu == M) != 0, 0) && mu == M) {
+                if (__builtin_expect((fire_lanes & lanes(mu == M)) != 0, 0) && fire && mu == M) {
                     // target at or above the total (rare): the last reaction with a positive propensity.
                     // The empty asm keeps this a branch: speculated, it would cost 2M ops every event.
                     __asm__ volatile("");
@@ -728,50 +742,50 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     }
                 }
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
-                const bool stop = !fire || n == n_stop;
-                if (__builtin_expect(__ballot(stop) != 0, 0) && stop) {
-                    // ---- finish (or suspend) this trajectory, once per trajectory
-                    int status;
-                    if (!a_ok)
-                        status = !m_ok ? (!(mrun <= 3.40282347e38f) ? ST_OVERFLOW : ST_ABSORBED)
-                                       : (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
-                                              ? ST_OVERFLOW
-                                              : ST_ABSORBED);
-                    else if (!fire)
-                        status = t_new > t_end ? ST_DONE : ST_SUSPENDED;
-                    else
-                        status = ST_CAPPED;
-                    if (status != ST_SUSPENDED) {
-                        for (; k < L.k_hi; ++k)
+                const bool stop = active && (!fire || n == n_stop);
+                if (__builtin_expect((act & (~fire_lanes | lanes(n == n_stop))) != 0, 0)) {
+                    if (stop) {
+                        // ---- finish (or suspend) this trajectory, once per trajectory
+                        int status;
+                        if (!a_ok)
+                            status = !m_ok ? (!(mrun <= 3.40282347e38f) ? ST_OVERFLOW : ST_ABSORBED)
+                                           : (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
+                                                  ? ST_OVERFLOW
+                                                  : ST_ABSORBED);
+                        else if (!fire)
+                            status = t_new > t_end ? ST_DONE : ST_SUSPENDED;
+                        else
+                            status = ST_CAPPED;
+                        if (status != ST_SUSPENDED) {
+                            for (; k < L.k_hi; ++k)
+#pragma unroll
+                                for (int s = 0; s < N; ++s)
+                                    I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
+                            I.n_events[idx] = n;
+                            I.t_last[idx] = (double)t;
+                        }
+                        I.status[idx] = (unsigned char)status;
+                        if (I.work)
+                            I.work[idx] = (u32)(n - n_claim);
+                        if constexpr (Md::REC != 0)
+                            I.rec_n[idx] = rec_cnt;
+                        if (!L.last) {
 #pragma unroll
                             for (int s = 0; s < N; ++s)
-                                I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
-                        I.n_events[idx] = n;
-                        I.t_last[idx] = (double)t;
+                                I.cx[(u64)s * I.E + idx] = x[s];
+                            I.ct[idx] = (double)t;
+                            I.cn[idx] = n;
+                            I.ck[idx] = k;
+                            I.cm[idx] = mrun;
+                        }
+                        active = false;
                     }
-                    I.status[idx] = (unsigned char)status;
-                    if (I.work)
-                        I.work[idx] = (u32)(n - n_claim);
-                    if constexpr (Md::REC != 0)
-                        I.rec_n[idx] = rec_cnt;
-                    if (!L.last) {
-#pragma unroll
-                        for (int s = 0; s < N; ++s)
-                            I.cx[(u64)s * I.E + idx] = x[s];
-                        I.ct[idx] = (double)t;
-                        I.cn[idx] = n;
-                        I.ck[idx] = k;
-                        I.cm[idx] = mrun;
-                    }
-                    active = false;
-                    stopped = true;
+                    // leave to claim new trajectories once a lane stops (while any
+                    // are left), or when every lane has stopped
+                    act = lanes(active);
+                    if (open || act == 0)
+                        break;
                 }
-            }
-            // leave to claim new trajectories once a lane stops (while any are
-            // left), or when every lane has stopped
-            if (__builtin_expect(__ballot(stopped) != 0, 0)) {
-                if (open || __ballot(active) == 0)
-                    break;
             }
         }
     }
