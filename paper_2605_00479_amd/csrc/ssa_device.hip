@@ -628,7 +628,12 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
         // lane never fires, stores nothing and leaves its registers unused, and
         // the step needs no exec-mask save and restore around it.
         for (;;) {
-            {   // one event step
+            // the last event's values, from which a stopping lane's status is read
+            A a0 = 0;
+            Tm t_new = 0;
+            bool a_ok = false, m_ok = true, fire = false;
+            u64 stop_lanes;
+            do {   // one event step per iteration, until some lane stops
                 // ---- draws: cur belongs to event n; event n+1's is formed alongside
                 const u32 id = I.id_base + idx;
                 const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
@@ -658,7 +663,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 }
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
-                bool m_ok = true;
+                m_ok = true;
                 if constexpr (P::NORM) {
                     float mx = 0.0f;
 #pragma unroll
@@ -677,16 +682,14 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
 #pragma unroll
                 for (int j = 1; j < M; ++j)
                     S[j] = P::acc(S[j - 1], a[j], pool.hw(SLOT_SUM + j - 1));
-                const A a0 = S[M - 1];
+                a0 = S[M - 1];
                 // a0 in (0, largest finite]: false for zero, negatives, infinity and NaN
-                bool a_ok;
                 if constexpr (P::WIDE)   // positive finite binary64: bit patterns 1 .. 0x7FEFFFFFFFFFFFFF
                     a_ok = (u64)__double_as_longlong(a0) - 1ull < 0x7FEFFFFFFFFFFFFFull;
                 else
                     a_ok = __float_as_uint(a0) - 1u < 0x7F7FFFFFu;
                 a_ok = a_ok && m_ok;
                 // ---- waiting time and clock (formed on every lane, used only if the event fires)
-                Tm t_new;
                 if constexpr (P::UNI) {
                     A tau = P::arnd(P::tau_div(cur.L, a0), pool.hw(SLOT_TAU));
                     if constexpr (P::NORM)
@@ -709,7 +712,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     } while (t_next < t_new);
                     t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
                 }
-                const bool fire = active && a_ok && t_new <= t_stop;
+                fire = active && a_ok && t_new <= t_stop;
                 const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
                 // ---- selection: mu = number of prefix sums at or below the target
                 const A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
@@ -742,51 +745,49 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                     }
                 }
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
-                const bool stop = active && (!fire || n == n_stop);
-                if (__builtin_expect((act & (~fire_lanes | lanes(n == n_stop))) != 0, 0)) {
-                    if (stop) {
-                        // ---- finish (or suspend) this trajectory, once per trajectory
-                        int status;
-                        if (!a_ok)
-                            status = !m_ok ? (!(mrun <= 3.40282347e38f) ? ST_OVERFLOW : ST_ABSORBED)
-                                           : (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
-                                                  ? ST_OVERFLOW
-                                                  : ST_ABSORBED);
-                        else if (!fire)
-                            status = t_new > t_end ? ST_DONE : ST_SUSPENDED;
-                        else
-                            status = ST_CAPPED;
-                        if (status != ST_SUSPENDED) {
-                            for (; k < L.k_hi; ++k)
+                stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
+            } while (__builtin_expect(stop_lanes == 0, 1));
+            if (active && (!fire || n == n_stop)) {
+                // ---- finish (or suspend) this trajectory, once per trajectory
+                int status;
+                if (!a_ok)
+                    status = !m_ok ? (!(mrun <= 3.40282347e38f) ? ST_OVERFLOW : ST_ABSORBED)
+                                   : (!(a0 <= (P::WIDE ? (A)1.7976931348623157e308 : (A)3.40282347e38f))
+                                          ? ST_OVERFLOW
+                                          : ST_ABSORBED);
+                else if (!fire)
+                    status = t_new > t_end ? ST_DONE : ST_SUSPENDED;
+                else
+                    status = ST_CAPPED;
+                if (status != ST_SUSPENDED) {
+                    for (; k < L.k_hi; ++k)
 #pragma unroll
-                                for (int s = 0; s < N; ++s)
-                                    I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
-                            I.n_events[idx] = n;
-                            I.t_last[idx] = (double)t;
-                        }
-                        I.status[idx] = (unsigned char)status;
-                        if (I.work)
-                            I.work[idx] = (u32)(n - n_claim);
-                        if constexpr (Md::REC != 0)
-                            I.rec_n[idx] = rec_cnt;
-                        if (!L.last) {
-#pragma unroll
-                            for (int s = 0; s < N; ++s)
-                                I.cx[(u64)s * I.E + idx] = x[s];
-                            I.ct[idx] = (double)t;
-                            I.cn[idx] = n;
-                            I.ck[idx] = k;
-                            I.cm[idx] = mrun;
-                        }
-                        active = false;
-                    }
-                    // leave to claim new trajectories once a lane stops (while any
-                    // are left), or when every lane has stopped
-                    act = lanes(active);
-                    if (open || act == 0)
-                        break;
+                        for (int s = 0; s < N; ++s)
+                            I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
+                    I.n_events[idx] = n;
+                    I.t_last[idx] = (double)t;
                 }
+                I.status[idx] = (unsigned char)status;
+                if (I.work)
+                    I.work[idx] = (u32)(n - n_claim);
+                if constexpr (Md::REC != 0)
+                    I.rec_n[idx] = rec_cnt;
+                if (!L.last) {
+#pragma unroll
+                    for (int s = 0; s < N; ++s)
+                        I.cx[(u64)s * I.E + idx] = x[s];
+                    I.ct[idx] = (double)t;
+                    I.cn[idx] = n;
+                    I.ck[idx] = k;
+                    I.cm[idx] = mrun;
+                }
+                active = false;
             }
+            // leave to claim new trajectories once a lane stops (while any are
+            // left), or when every lane has stopped
+            act = lanes(active);
+            if (open || act == 0)
+                break;
         }
     }
 }
