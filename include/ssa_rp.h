@@ -161,7 +161,11 @@ typedef struct ssa_item {
  *     this kernel and workload shape if ssa_autotune stored one, else 1.
  *   block_size, grid_size: launch shape; 0 = the autotuned choice if stored,
  *     else 256 threads and enough workgroups for one trajectory per lane (up
- *     to what stays resident). block_size a multiple of 64 up to 256.
+ *     to what stays resident). block_size a multiple of 64 up to 256, or 512:
+ *     then waves 0-3 of each workgroup run trajectories and wave w + 4, on
+ *     the same SIMD as wave w, forms wave w's random draws ahead of use and
+ *     passes them through LDS (results are bit-identical: the draws are the
+ *     same function of seed, trajectory and event index).
  *   reorder: chunked runs only. 0 or 1: before each chunk after the first,
  *     trajectories are claimed in order of the events they fired in the
  *     previous chunk, heaviest first (results are unchanged: draws are keyed

@@ -281,15 +281,82 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
     o << "typedef " << ms.policy() << " PrecRun;\n"
       << "extern \"C\" __global__ void __launch_bounds__(256) ssa_kernel(LaunchArgs L) {\n"
       << "  const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n"
+      << "  SelfFeed feed;\n"
       << "  u32 it = wave % SSA_N_ITEMS;\n"
       << "  for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "    switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
         o << "    case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
-          << ">(L, L.item[" << i << "]); break;\n";
+          << ">(L, L.item[" << i << "], feed); break;\n";
     o << "    default: break;\n"
       << "    }\n"
       << "    it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "  }\n"
+      << "}\n";
+    // 512-thread workgroups: waves 0-3 run the event loop, wave w + 4 (on the
+    // same SIMD as wave w) forms wave w's draws ahead into an LDS ring
+    o << "constexpr int SSA_RING_NW = ";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << (i ? ", " : "") << (i + 1 < models.size() ? "cmax(" : "")
+          << "DrawIO<PrecRun, Slots<PrecRun, Md" << i << ">::NSLOT>::NW";
+    for (size_t i = 1; i < models.size(); ++i)
+        o << ")";
+    o << ";\n"
+      << "constexpr int SSA_RING_D = ring_depth(SSA_RING_NW);\n"
+      << "extern \"C\" __global__ void __launch_bounds__(512) ssa_kernel_pc(LaunchArgs L) {\n"
+      << "  const u32 w = threadIdx.x >> 6, c = w & 3u, lane = lane_id();\n"
+      << "  if constexpr (SSA_RING_D == 0) {\n"
+      << "    SelfFeed feed;\n"
+      << "    u32 it = (blockIdx.x * 8u + w) % SSA_N_ITEMS;\n"
+      << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
+      << "      switch (it) {\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << "      case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
+          << ">(L, L.item[" << i << "], feed); break;\n";
+    o << "      default: break;\n"
+      << "      }\n"
+      << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "    }\n"
+      << "    return;\n"
+      << "  } else {\n"
+      << "  __shared__ RingCtl ctl[4];\n"
+      << "  __shared__ u32 ring[4 * (SSA_RING_D > 0 ? SSA_RING_D : 1) * SSA_RING_NW * 64];\n"
+      << "  if (w < 4) {\n"
+      << "    ctl[c].req_e[lane] = 0u;\n"
+      << "    ctl[c].done[lane] = 0u;\n"
+      << "    ctl[c].item = 0u;\n"
+      << "  } else {\n"
+      << "    ctl[c].made[lane] = 0u;\n"
+      << "  }\n"
+      << "  __syncthreads();\n"
+      << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
+      << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
+      << "  if (w < 4) {\n"
+      << "    __builtin_amdgcn_s_setprio(3);\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u};\n"
+      << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
+      << "      lds_st(&ctl[c].item, i);\n"
+      << "      lgkm_wait();\n"
+      << "      switch (it) {\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << "      case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
+          << ">(L, L.item[" << i << "], feed); break;\n";
+    o << "      default: break;\n"
+      << "      }\n"
+      << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "    }\n"
+      << "    lds_st(&ctl[c].item, ~0u);\n"
+      << "  } else {\n"
+      << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
+      << "      switch (it) {\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << "      case " << i << ": produce_item<PrecRun, Md" << i
+          << ", SSA_RING_D, SSA_RING_NW>(L, L.item[" << i << "], &ctl[c], my_ring, i); break;\n";
+    o << "      default: break;\n"
+      << "      }\n"
+      << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "    }\n"
+      << "  }\n"
       << "  }\n"
       << "}\n"
       << "extern \"C\" __global__ void ssa_fill_u32(u32 *p, u32 n, u32 v) {\n"
@@ -393,6 +460,7 @@ int compile_source(const std::string &src, const std::string &arch, std::vector<
 struct Loaded {
     hipModule_t mod = nullptr;
     hipFunction_t kernel = nullptr;
+    hipFunction_t kernel_pc = nullptr;   // 512-thread workgroups: event-loop waves paired with draw producers
     hipFunction_t fill = nullptr;
     hipFunction_t rg_hist = nullptr, rg_scan = nullptr, rg_scatter = nullptr;
     int vgprs = -1;
@@ -420,6 +488,7 @@ int get_kernel(const std::string &src, Loaded &out)
     Loaded ld;
     HIP_TRY(hipModuleLoadData(&ld.mod, code.data()));
     HIP_TRY(hipModuleGetFunction(&ld.kernel, ld.mod, "ssa_kernel"));
+    HIP_TRY(hipModuleGetFunction(&ld.kernel_pc, ld.mod, "ssa_kernel_pc"));
     HIP_TRY(hipModuleGetFunction(&ld.fill, ld.mod, "ssa_fill_u32"));
     HIP_TRY(hipModuleGetFunction(&ld.rg_hist, ld.mod, "ssa_regroup_hist"));
     HIP_TRY(hipModuleGetFunction(&ld.rg_scan, ld.mod, "ssa_regroup_scan"));
@@ -584,8 +653,9 @@ int validate_desc(const ssa_run_desc *d)
         return rc;
     if (d->n_chunks < 0 || d->n_chunks > 4096)
         return fail(SSA_E_INVALID, "n_chunks must be in [0, 4096]");
-    if (d->block_size != 0 && (d->block_size < 64 || d->block_size > 256 || d->block_size % 64 != 0))
-        return fail(SSA_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
+    if (d->block_size != 0 && d->block_size != 512 &&
+        (d->block_size < 64 || d->block_size > 256 || d->block_size % 64 != 0))
+        return fail(SSA_E_INVALID, "block_size must be 0, a multiple of 64 in [64, 256], or 512");
     if (d->grid_size < 0)
         return fail(SSA_E_INVALID, "grid_size must be >= 0");
     if (d->reorder < -1 || d->reorder > 1)
@@ -848,7 +918,8 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
         void *args[] = {&A};
         if (!r->graph)
             HIP_TRY(hipEventRecord(r->kev[2 * c], s));
-        HIP_TRY(hipModuleLaunchKernel(ld.kernel, r->grid, 1, 1, r->block, 1, 1, 0, s, args, nullptr));
+        HIP_TRY(hipModuleLaunchKernel(r->block == 512 ? ld.kernel_pc : ld.kernel, r->grid, 1, 1, r->block, 1, 1, 0,
+                                      s, args, nullptr));
         if (!r->graph)
             HIP_TRY(hipEventRecord(r->kev[2 * c + 1], s));
         // claim order for the next chunk: heaviest trajectories of this chunk first
@@ -1039,10 +1110,13 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
     r->block = d->block_size ? d->block_size : (have_tuned ? tuned.block : 256);
     int per_cu = 0;
-    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel, r->block, 0));
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, r->block == 512 ? ld.kernel_pc : ld.kernel,
+                                                              r->block, 0));
     if (per_cu < 1)
         per_cu = 1;
-    int64_t need = (total + r->block - 1) / r->block;
+    // lanes running the event loop per workgroup (half of a 512-thread one)
+    const int loop_lanes = r->block == 512 ? 256 : r->block;
+    int64_t need = (total + loop_lanes - 1) / loop_lanes;
     int64_t resident = (int64_t)per_cu * cus;
     int64_t grid = d->grid_size ? d->grid_size
                                 : (have_tuned && tuned.block == r->block ? tuned.grid
@@ -1361,6 +1435,18 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         for (int64_t g : grids)
             for (const ChunkOpt &ch : chunk_opts)
                 cands.push_back({block, (int)g, ch.chunks, ch.window});
+    }
+    // 512-thread workgroups: one event-loop wave per SIMD, each paired with
+    // the wave that forms its draws
+    {
+        int per_cu = 0;
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel_pc, 512, 0));
+        if (per_cu >= 1) {
+            const int64_t need = std::max<int64_t>(1, (total + 255) / 256);
+            const int64_t g = std::min<int64_t>(need, cus);
+            for (const ChunkOpt &ch : chunk_opts)
+                cands.push_back({512, (int)g, ch.chunks, ch.window});
+        }
     }
     cands.erase(std::unique(cands.begin(), cands.end(),
                             [](const Cand &a, const Cand &b) {

@@ -243,6 +243,17 @@ struct PrecF32 {
     __device__ static A tau_div(A l, A a0) { return l / a0; }
 };
 
+// v as computed in binary32. An operation followed by a conversion to fp16 may
+// otherwise be fused into one v_fma_mixlo_f16, which rounds the exact result
+// once where the op and the conversion round twice. For +, -, x, / of two fp16
+// values the two agree; where an operand has more bits (u2 in the selection
+// target) they can differ at a tie of the second rounding.
+__device__ __forceinline__ float f32_kept(float v)
+{
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
 template <int FMT, bool SRM>
 __device__ __forceinline__ float rnd16(float v, u32 rb)
 {
@@ -504,28 +515,257 @@ __device__ __forceinline__ typename P::Tm snap_time(const LaunchArgs &L, int k)
 }
 
 // --------------------------------------------------------------------------
+// Rounding slots of an event (Md: generated network description). With
+// selective SR only the M-1 partial sums and the clock draw.
+// --------------------------------------------------------------------------
+template <class P, class Md>
+struct Slots {
+    static constexpr int M = Md::M;
+    static constexpr int NSLOT = !P::SR ? 0
+                                 : (P::SELECTIVE ? M : Md::NPROP + (P::UNI ? (P::NORM ? 2 * M + 4 : M + 3) : 0));
+    static constexpr int NORM = Md::NPROP;
+    static constexpr int SUM = P::SELECTIVE ? 0 : Md::NPROP + (P::NORM ? M : 0);
+    static constexpr int LOG = SUM + M - 1;
+    static constexpr int TAU = LOG + 1;
+    static constexpr int TAUM = TAU + 1;
+    static constexpr int TIME = P::SELECTIVE ? M - 1 : TAU + 1 + (P::NORM ? 1 : 0);
+    static constexpr int TARGET = TIME + 1;
+};
+
+// A draw as 32-bit words: the pool's words, then L and u2 (one word each in
+// binary32, two in binary64). Word k of a stored draw sits at w[64 k], so the
+// 64 lanes of a wave touch 64 consecutive words.
+template <class P, int NSLOT>
+struct DrawIO {
+    static constexpr int NP = NSLOT > 0 ? Pool<NSLOT, P::SR_B>::NW : 0;
+    static constexpr int NA = (int)(sizeof(typename P::A) / 4);
+    static constexpr int NW = NP + 2 * NA;
+
+    __device__ static void store(u32 *w, const Draw<P, NSLOT> &d)
+    {
+        if constexpr (NP > 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                w[64 * k] = d.pool.w[k];
+        }
+        if constexpr (NA == 1) {
+            w[64 * NP] = __float_as_uint((float)d.L);
+            w[64 * (NP + 1)] = __float_as_uint((float)d.u2);
+        } else {
+            const u64 a = (u64)__double_as_longlong((double)d.L), b = (u64)__double_as_longlong((double)d.u2);
+            w[64 * NP] = (u32)a;
+            w[64 * (NP + 1)] = (u32)(a >> 32);
+            w[64 * (NP + 2)] = (u32)b;
+            w[64 * (NP + 3)] = (u32)(b >> 32);
+        }
+    }
+
+    __device__ static void load(const u32 *w, Draw<P, NSLOT> &d)
+    {
+        if constexpr (NP > 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                d.pool.w[k] = w[64 * k];
+        }
+        if constexpr (NA == 1) {
+            d.L = __uint_as_float(w[64 * NP]);
+            d.u2 = __uint_as_float(w[64 * (NP + 1)]);
+        } else {
+            d.L = __longlong_as_double((long long)(((u64)w[64 * (NP + 1)] << 32) | w[64 * NP]));
+            d.u2 = __longlong_as_double((long long)(((u64)w[64 * (NP + 3)] << 32) | w[64 * (NP + 2)]));
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
+// Draw feeds. The event loop takes event n + 1's draw while it runs event n.
+// SelfFeed forms it in the same wave. RingFeed takes it from a ring in LDS
+// that a producer wave on the same SIMD fills ahead (produce_item), and forms
+// it itself wherever the ring does not hold it: the event loop never waits
+// for the producer. The producer makes exactly the draws the loop would form
+// (same function of seed, trajectory and event index), so results do not
+// depend on the feed.
+//
+// Protocol, per lane (consumer lane l and producer lane l of the paired waves):
+//   req_*  consumer -> producer: trajectory id and claim event index, then the
+//          epoch e (1..255, new at every claim) once the rest is written;
+//   done   consumer -> producer: (e << 24) | low 24 bits of the first draw the
+//          consumer has not read yet;
+//   made   producer -> consumer: (e << 24) | low 24 bits of the first draw not
+//          made yet; draws [made - D, made) of epoch e are in the ring.
+// The producer writes draw p only while p < done + D, so a draw the consumer
+// finds made stays in place until it has read it. Ordering rests on waits for
+// completed LDS operations (lgkmcnt 0): the producer waits for its ring
+// stores before it updates made, the consumer waits for its made load before
+// it loads ring words, and for its ring loads before it updates done.
+// --------------------------------------------------------------------------
+struct RingCtl {
+    u32 made[64];
+    u32 done[64];
+    u32 req_e[64];
+    u32 req_id[64];
+    u32 req_lo[64];
+    u32 req_hi[64];
+    u32 item;        // consumer -> producer: sequence number of the item in progress (~0u: finished)
+};
+
+__device__ __forceinline__ void lgkm_wait()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+    __asm__ volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ u32 lds_ld(const u32 *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_st(u32 *p, u32 v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+struct SelfFeed {
+    static constexpr bool RING = false;
+    __device__ void claim(u32, u64) {}
+};
+
+template <int D, int NWMAX>
+struct RingFeed {
+    static constexpr bool RING = true;
+    RingCtl *ctl;   // this consumer wave's control words
+    u32 *ring;      // [D][NWMAX][64]
+    u32 lane;
+    u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
+
+    // a new trajectory on this lane; the loop forms draws n and n + 1 itself
+    __device__ void claim(u32 id, u64 n)
+    {
+        eb = eb % 255u + 1u;
+        lds_st(&ctl->done[lane], (eb << 24) | ((u32)(n + 1) & 0xFFFFFFu));
+        lds_st(&ctl->req_id[lane], id);
+        lds_st(&ctl->req_lo[lane], (u32)n);
+        lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
+        lgkm_wait();
+        lds_st(&ctl->req_e[lane], eb);
+    }
+
+    __device__ u32 made_word() const { return lds_ld(&ctl->made[lane]); }
+
+    // ring words of draw `want` (valid where finish finds the draw made)
+    template <class P, int NSLOT>
+    __device__ void read(u64 want, Draw<P, NSLOT> &d) const
+    {
+        lgkm_wait();   // the made word, and the previous draw's ring words, are in
+        lds_st(&ctl->done[lane], (eb << 24) | ((u32)want & 0xFFFFFFu));
+        DrawIO<P, NSLOT>::load(ring + ((u32)want & (u32)(D - 1)) * (NWMAX * 64) + lane, d);
+    }
+
+    // where the ring did not hold draw `want` of this trajectory, form it here
+    template <class P, int NSLOT, int SLOT_LOG>
+    __device__ void finish(Draw<P, NSLOT> &d, u32 mw, u64 want, u32 id, u64 act, u32 k0, u32 k1) const
+    {
+        const bool e_ok = (mw >> 24) == eb;
+        const bool r_ok = ((mw - (u32)want) & 0xFFFFFFu) - 1u < (u32)D;   // want < made <= want + D
+        if (__builtin_expect((act & ~(lanes(e_ok) & lanes(r_ok))) != 0, 0)) {
+            __asm__ volatile("");
+            const Draw<P, NSLOT> s = make_draw<P, NSLOT, SLOT_LOG>(want, id, k0, k1);
+            if (!(e_ok && r_ok))
+                d = s;
+        }
+    }
+};
+
+// Producer wave of one item: for each lane, the draws of its consumer lane's
+// trajectory from the claim's event index + 1 on, up to D ahead of the
+// consumer, formed in batches of up to four independent draws (their Philox
+// and logarithm chains overlap). Returns once the consumer has moved past
+// item `seq`.
+template <class P, class Md, int D, int NWMAX>
+__device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ctl, u32 *ring, u32 seq)
+{
+    typedef Slots<P, Md> S;
+    typedef DrawIO<P, S::NSLOT> IO;
+    constexpr int BATCH = D < 4 ? D : 4;
+    const u32 lane = lane_id();
+    u32 e = 0, id = 0;
+    u64 p = 0;
+    for (;;) {
+        const u32 re = lds_ld(&ctl->req_e[lane]);
+        lgkm_wait();   // a new epoch's request words were written before it
+        const u32 item = __builtin_amdgcn_readfirstlane(lds_ld(&ctl->item));
+        const u32 rid = lds_ld(&ctl->req_id[lane]);
+        const u32 rlo = lds_ld(&ctl->req_lo[lane]), rhi = lds_ld(&ctl->req_hi[lane]);
+        const u32 dw = lds_ld(&ctl->done[lane]);
+        if (item != seq)
+            break;
+        if (re != e) {
+            e = re;
+            id = rid;
+            p = (((u64)rhi << 32) | rlo) + 1;
+        }
+        const u32 ahead = ((u32)p - dw) & 0xFFFFFFu;   // draws made and not yet read
+        const u32 room = (e != 0 && (dw >> 24) == e && ahead < (u32)D) ? (u32)D - ahead : 0u;
+        if (__builtin_amdgcn_ballot_w64(room != 0u) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        Draw<P, S::NSLOT> d[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b)
+            d[b] = make_draw<P, S::NSLOT, S::LOG>(p + (u64)b, id, L.seed_lo, L.seed_hi);
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b)
+            if ((u32)b < room)
+                IO::store(ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * (NWMAX * 64) + lane, d[b]);
+        const u32 k = room < (u32)BATCH ? room : (u32)BATCH;
+        lgkm_wait();
+        if (k != 0u) {
+            lds_st(&ctl->made[lane], (e << 24) | ((u32)(p + k) & 0xFFFFFFu));
+            p += k;
+        }
+    }
+    (void)I;
+}
+
+// Ring depth for draws of nw words: the largest power of two up to 8 whose
+// four rings fit 56 KiB of LDS; 0 where not even a depth of 2 fits (then the
+// 512-thread kernel runs eight event-loop waves that form their own draws).
+__host__ __device__ constexpr int ring_depth(int nw)
+{
+    int d = 8;
+    while (d >= 2 && 4 * d * nw * 64 * 4 > 57344)
+        d /= 2;
+    return d >= 2 ? d : 0;
+}
+
+__host__ __device__ constexpr int cmax(int a, int b)
+{
+    return a > b ? a : b;
+}
+
+// --------------------------------------------------------------------------
 // One wave works through one item: lanes claim trajectories from the item's
 // counter, run events, and claim again as they finish (ballot + prefix rank,
 // one atomic per refill), until the counter passes E and every lane is idle.
 // Md: generated network description; P: precision policy.
 // --------------------------------------------------------------------------
-template <class P, class Md, bool PER_LANE_RATES>
-__device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
+template <class P, class Md, bool PER_LANE_RATES, class F>
+__device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
 {
     typedef typename P::T T;
     typedef typename P::A A;
     typedef typename P::Tm Tm;
+    typedef Slots<P, Md> S;
     constexpr int N = Md::N, M = Md::M;
-    // rounding slots: with selective SR only the M-1 partial sums and the clock draw
-    constexpr int NSLOT = !P::SR ? 0
-                          : (P::SELECTIVE ? M : Md::NPROP + (P::UNI ? (P::NORM ? 2 * M + 4 : M + 3) : 0));
-    constexpr int SLOT_NORM = Md::NPROP;
-    constexpr int SLOT_SUM = P::SELECTIVE ? 0 : Md::NPROP + (P::NORM ? M : 0);
-    constexpr int SLOT_LOG = SLOT_SUM + M - 1;
-    constexpr int SLOT_TAU = SLOT_LOG + 1;
-    constexpr int SLOT_TAUM = SLOT_TAU + 1;
-    constexpr int SLOT_TIME = P::SELECTIVE ? M - 1 : SLOT_TAU + 1 + (P::NORM ? 1 : 0);
-    constexpr int SLOT_TARGET = SLOT_TIME + 1;
+    constexpr int NSLOT = S::NSLOT;
+    constexpr int SLOT_NORM = S::NORM;
+    constexpr int SLOT_SUM = S::SUM;
+    constexpr int SLOT_LOG = S::LOG;
+    constexpr int SLOT_TAU = S::TAU;
+    constexpr int SLOT_TAUM = S::TAUM;
+    constexpr int SLOT_TIME = S::TIME;
+    constexpr int SLOT_TARGET = S::TARGET;
 
     const T *rates = (const T *)I.rates;
     const T *hill = (const T *)I.hill;
@@ -611,6 +851,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                         t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
                         n_claim = n;
                         cur = make_draw<P, NSLOT, SLOT_LOG>(n, I.id_base + id, L.seed_lo, L.seed_hi);
+                        feed.claim(I.id_base + id, n);
                     }
                 }
                 if (base + cnt >= I.E)
@@ -634,9 +875,16 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
             bool a_ok = false, m_ok = true, fire = false;
             u64 stop_lanes;
             do {   // one event step per iteration, until some lane stops
-                // ---- draws: cur belongs to event n; event n+1's is formed alongside
+                // ---- draws: cur belongs to event n; event n+1's is formed (or
+                // taken from the producer's ring) alongside
                 const u32 id = I.id_base + idx;
-                const Draw<P, NSLOT> nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
+                const u64 want = n + 1;
+                Draw<P, NSLOT> nxt;
+                u32 made_w = 0;
+                if constexpr (F::RING)
+                    made_w = feed.made_word();
+                else
+                    nxt = make_draw<P, NSLOT, SLOT_LOG>(want, id, L.seed_lo, L.seed_hi);
                 const Pool<NSLOT, P::SR_B> &pool = cur.pool;
                 // ---- propensities (generated op sequence). Conversions of
                 // counts draw random bits only when they round: when every
@@ -661,6 +909,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 } else {
                     Md::template propensities<P, false>(x, c, hill, a, pool, NoConv());
                 }
+                if constexpr (F::RING)
+                    feed.read(want, nxt);
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
                 m_ok = true;
@@ -715,7 +965,11 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                 fire = active && a_ok && t_new <= t_stop;
                 const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
                 // ---- selection: mu = number of prefix sums at or below the target
-                const A target = P::arnd(cur.u2 * a0, pool.hw(SLOT_TARGET));
+                A target;
+                if constexpr (P::UNI)   // binary32 product, then one rounding to the 16-bit type
+                    target = P::arnd(f32_kept(cur.u2 * a0), pool.hw(SLOT_TARGET));
+                else
+                    target = cur.u2 * a0;
                 int mu = 0;
 #pragma unroll
                 for (int j = 0; j < M; ++j)
@@ -744,6 +998,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I)
                         ++rec_cnt;
                     }
                 }
+                if constexpr (F::RING)
+                    feed.template finish<P, NSLOT, SLOT_LOG>(nxt, made_w, want, id, act, L.seed_lo, L.seed_hi);
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
                 stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
             } while (__builtin_expect(stop_lanes == 0, 1));

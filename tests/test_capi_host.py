@@ -87,6 +87,8 @@ def test_run_descriptor_validation():
     assert _run_rc(mode="MIX_F16_SR", _fields={"rounding": 2}) == ssa.SSA_E_UNSUPPORTED
     assert _run_rc(mode="UNI_F16_SR", _fields={"rounding": 3}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"block_size": 100}) == ssa.SSA_E_INVALID
+    assert _run_rc(_fields={"block_size": 320}) == ssa.SSA_E_INVALID    # above 256, and not the paired 512
+    assert _run_rc(_fields={"block_size": 1024}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"n_items": 0}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"traj_id_base": 2**32 - 5}) == ssa.SSA_E_INVALID
     assert _run_rc(_fields={"reorder": 2}) == ssa.SSA_E_INVALID

@@ -70,6 +70,20 @@ def test_schlogl_modes(gpu, orc, mode):
     run_both(gpu, orc, it.model, it.x0, 1500, W.t_end, W.snap_t, mode, seed=W.seed, max_events=W.max_events)
 
 
+@pytest.mark.parametrize("mode,cap", [("UNI_F16_SRA", 0), ("UNI_F16_SR", 0), ("UNI_F16_RTN", 100_000),
+                                      ("UNI_BF16_SR_NORM", 0)])
+def test_schlogl_uniform_modes(gpu, orc, mode, cap):
+    """Uniform 16-bit runs of the Schloegl network. Its totals reach several
+    thousand, where the selection target (the binary32 product u2 * a0,
+    then one rounding to the 16-bit type) meets ties of the second rounding
+    (u2 has 24 bits, so rounding the exact product once can differ).
+    Round to nearest stalls the clock: capped runs."""
+    W = wl.config_schlogl()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, 1500, W.t_end, W.snap_t, mode, seed=W.seed,
+             max_events=cap or W.max_events)
+
+
 @pytest.mark.parametrize("mode", ["UNI_F16_RTN", "UNI_F16_SR", "UNI_F16_SR_NORM", "UNI_BF16_RTN",
                                   "UNI_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_RTN_NORM", "FP64",
                                   "UNI_F16_SRA", "UNI_BF16_SRA_NORM"])
@@ -259,12 +273,91 @@ def test_multi_item_batch_matches_oracle_per_item(gpu, orc):
 
 
 def test_full_size_schlogl_sampled(gpu, orc):
-    """The benchmark workload (100,000 trajectories, default launch) on a
-    sample of trajectory ids spread over the whole range."""
+    """The benchmark workload (100,000 trajectories) on a sample of trajectory
+    ids spread over the whole range, in the default launch and in the
+    benchmark's launch shapes: one event-loop wave per SIMD forming its own
+    draws (1024 waves of 64) or paired with a draw-producing wave (256
+    workgroups of 512), two snapshot windows with a first window of 10 rows."""
     W = wl.config_schlogl()
     it = W.items[0]
     sample = np.unique(np.concatenate([np.arange(0, 100_000, 997), [99_999, 65_535, 65_536]]))
+    launches = ({}, dict(block_size=64, grid_size=1024, n_chunks=2, first_window=10),
+                dict(block_size=512, grid_size=256, n_chunks=2, first_window=10))
     for mode in ("FP64", "MIX_F16_SR"):
-        run, snap, st = run_both(gpu, orc, it.model, it.x0, it.n_traj, W.t_end, W.snap_t, mode, seed=W.seed,
-                                 max_events=W.max_events, indices=sample)
-        assert np.all(run.stats(0)["status"] == 0)
+        for launch in launches:
+            run, snap, st = run_both(gpu, orc, it.model, it.x0, it.n_traj, W.t_end, W.snap_t, mode, seed=W.seed,
+                                     max_events=W.max_events, indices=sample, **launch)
+            assert np.all(run.stats(0)["status"] == 0)
+
+
+# ---------------------------------------------------------------------------
+# Producer waves (block_size 512): waves 0-3 of a workgroup run trajectories,
+# wave w + 4 forms wave w's draws ahead through an LDS ring. Same results as
+# every other launch shape, so the same oracle bar.
+# ---------------------------------------------------------------------------
+PC = dict(block_size=512)
+
+
+@pytest.mark.parametrize("mode", ["FP64", "FP32", "MIX_F16_SR", "MIX_BF16_SR", "UNI_BF16_SR_NORM", "UNI_F16_SRA"])
+def test_producer_waves_schlogl(gpu, orc, mode):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    run_both(gpu, orc, it.model, it.x0, 1500, W.t_end, W.snap_t, mode, seed=W.seed, max_events=W.max_events, **PC)
+
+
+def test_producer_waves_one_workgroup_refills(gpu, orc):
+    """One workgroup: four event-loop waves and their producers run 3,000
+    trajectories, so every lane claims many trajectories, each a new epoch of
+    its ring slots."""
+    W = wl.config_birth_death()
+    it = W.items[0]
+    for mode in ("MIX_F16_SR", "FP64", "UNI_F16_SR_NORM"):
+        run_both(gpu, orc, it.model, it.x0, 3000, 20.0, [5.0, 20.0], mode, seed=4, block_size=512, grid_size=1)
+
+
+@pytest.mark.parametrize("mode", ["MIX_F16_SR", "UNI_BF16_SRA"])
+def test_producer_waves_hill_laws(gpu, orc, mode):
+    m = wl.repressilator()
+    run_both(gpu, orc, m, np.array([0, 0, 0, 0, 0, 20], np.int32), 600, 60.0, wl.snapshot_grid(60.0, 61),
+             mode, seed=3, max_events=10_000_000, **PC)
+
+
+def test_producer_waves_count_conversion(gpu, orc):
+    levels, kd = (1500.0, 2100.0, 2600.0), 1.0
+    rates = np.array([[kb, kd] for kb in levels], np.float64)
+    run_both(gpu, orc, wl.birth_death(levels[1], kd), np.array([2100], np.int32), 3 * 70, 1.5,
+             wl.snapshot_grid(1.5, 7), "MIX_F16_SR", seed=11, set_rate=rates, traj_per_set=70,
+             max_events=200_000, **PC)
+
+
+def test_producer_waves_chunked_and_suspended(gpu, orc):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    for mode in ("MIX_F16_SR", "UNI_BF16_SR_NORM"):
+        for chunks, window in ((3, 0), (2, 5)):
+            run_both(gpu, orc, it.model, it.x0, 700, 5.0, wl.snapshot_grid(5.0, 51), mode, seed=6,
+                     max_events=W.max_events, n_chunks=chunks, first_window=window, **PC)
+
+
+def test_producer_waves_multi_item_batch(gpu, orc):
+    """Five networks in one launch: each event-loop wave hands its producer
+    from one item (and draw layout) to the next."""
+    W = wl.config_heterogeneous(n_traj_total=5 * 150)
+    t_end, ts = 15.0, wl.snapshot_grid(15.0, 16)
+    items = gpu.items_from_workload(W, {})
+    for mode, chunks, grid in (("FP64", 1, 0), ("MIX_F16_SR", 1, 1), ("UNI_F16_SR_NORM", 3, 0)):
+        print(f"[gpu-parity] producer waves, heterogeneous mode={mode} chunks={chunks} grid={grid}", flush=True)
+        run = gpu.ssa_ensemble_run(items, t_end, ts, 1, mode, traj_id_base=1000, max_events=W.max_events,
+                                   n_chunks=chunks, block_size=512, grid_size=grid)
+        base = 1000
+        for i, it in enumerate(W.items):
+            ref = orc.simulate(it.model, mode, it.x0, t_end, ts, 1, n_traj=it.n_traj, traj_id_base=base,
+                               max_events=W.max_events, threads=ORACLE_THREADS)
+            assert_parity(ref, run.snapshots(i), run.stats(i), mode, it.model.name)
+            base += it.n_traj
+
+
+def test_producer_waves_event_record(gpu, orc):
+    spec = wl.telegraph(0.05, 0.05, 20.0, 1.0)
+    x0 = np.array([1, 0, 0], np.int32)
+    run_records(gpu, orc, spec, x0, 300, 200.0, wl.snapshot_grid(200.0, 11), "MIX_F16_SR", 0b11, 12, seed=4, **PC)
