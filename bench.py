@@ -218,7 +218,10 @@ def main():
         fidelity["ks_pass_all"] = bool(all(v["independent_seeds"]["ks_p"] > 0.05
                                            for k, v in fidelity.items() if k != "ks_pass_all"))
 
-    # roofline: VALU slots of one event on the every-event path of the launched code object
+    # roofline: VALU slots of one event on the every-event path of the launched
+    # code object, counted on its one-wave event loop (ssa_kernel). With producer
+    # waves (ssa_kernel_pc, 512-thread workgroups) the same per-event work is
+    # split between the paired waves; the LDS ring traffic is not counted.
     def per_event(mode):
         f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode)
         return {**valu_count.count(f), "file": f}
@@ -263,10 +266,12 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS,
                      "traffic": measured_traffic(args.mode, ve["file"]),
-                     "kernel": "ssa_kernel", "kernel_object": os.path.basename(ve["file"]), "kernel_ms": ms,
+                     "kernel": "ssa_kernel_pc" if main_res["info"]["block_size"] == 512 else "ssa_kernel",
+                     "kernel_object": os.path.basename(ve["file"]), "kernel_ms": ms,
                      "valu_slots_per_event": ve["valu_slots"], "valu_insts_per_event": ve["valu_insts"]},
     }
     out["fp64"]["kernel_object"] = os.path.basename(ve_ref["file"])
+    out["fp64"]["kernel"] = "ssa_kernel_pc" if ref_res["info"]["block_size"] == 512 else "ssa_kernel"
     if args.valu_peak:
         out["valu_peak"] = valu_peak(log)
     if args.copy_calib:

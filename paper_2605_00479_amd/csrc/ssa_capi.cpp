@@ -463,7 +463,11 @@ struct Loaded {
     hipFunction_t kernel_pc = nullptr;   // 512-thread workgroups: event-loop waves paired with draw producers
     hipFunction_t fill = nullptr;
     hipFunction_t rg_hist = nullptr, rg_scan = nullptr, rg_scatter = nullptr;
-    int vgprs = -1;
+    int vgprs = -1, vgprs_pc = -1;
+    // dynamic LDS added to each ssa_kernel_pc workgroup (unused by the kernel) so
+    // that it holds more than half of a CU's LDS: one workgroup, i.e. one
+    // event-loop wave per SIMD, per CU, whatever the dispatcher would pack
+    unsigned pc_lds_pad = 0;
 };
 
 std::mutex g_jit_mu;
@@ -496,6 +500,17 @@ int get_kernel(const std::string &src, Loaded &out)
     int regs = -1;
     if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, ld.kernel) == hipSuccess)
         ld.vgprs = regs;
+    regs = -1;
+    if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, ld.kernel_pc) == hipSuccess)
+        ld.vgprs_pc = regs;
+    int lds_cu = 0, lds_block = 0, lds_static = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        hipFuncGetAttribute(&lds_static, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, ld.kernel_pc) == hipSuccess) {
+        const int want = lds_cu / 2 + 1024;
+        if (want > lds_static && want <= lds_block)
+            ld.pc_lds_pad = (unsigned)(want - lds_static);
+    }
     g_loaded[key] = ld;
     out = ld;
     return SSA_OK;
@@ -918,8 +933,8 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
         void *args[] = {&A};
         if (!r->graph)
             HIP_TRY(hipEventRecord(r->kev[2 * c], s));
-        HIP_TRY(hipModuleLaunchKernel(r->block == 512 ? ld.kernel_pc : ld.kernel, r->grid, 1, 1, r->block, 1, 1, 0,
-                                      s, args, nullptr));
+        HIP_TRY(hipModuleLaunchKernel(r->block == 512 ? ld.kernel_pc : ld.kernel, r->grid, 1, 1, r->block, 1, 1,
+                                      r->block == 512 ? ld.pc_lds_pad : 0u, s, args, nullptr));
         if (!r->graph)
             HIP_TRY(hipEventRecord(r->kev[2 * c + 1], s));
         // claim order for the next chunk: heaviest trajectories of this chunk first
@@ -1109,9 +1124,11 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, r->device));
     r->block = d->block_size ? d->block_size : (have_tuned ? tuned.block : 256);
+    if (r->block == 512)
+        r->vgprs = ld.vgprs_pc;
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, r->block == 512 ? ld.kernel_pc : ld.kernel,
-                                                              r->block, 0));
+                                                              r->block, r->block == 512 ? ld.pc_lds_pad : 0u));
     if (per_cu < 1)
         per_cu = 1;
     // lanes running the event loop per workgroup (half of a 512-thread one)
@@ -1440,7 +1457,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
     // the wave that forms its draws
     {
         int per_cu = 0;
-        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel_pc, 512, 0));
+        HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ld.kernel_pc, 512, ld.pc_lds_pad));
         if (per_cu >= 1) {
             const int64_t need = std::max<int64_t>(1, (total + 255) / 256);
             const int64_t g = std::min<int64_t>(need, cus);
