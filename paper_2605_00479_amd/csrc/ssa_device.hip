@@ -500,6 +500,21 @@ __device__ __forceinline__ u64 lanes(bool c)
     return __builtin_amdgcn_ballot_w64(c);
 }
 
+// A wave-uniform value moved to a scalar register.
+template <class V>
+__device__ __forceinline__ V uniform_value(V v)
+{
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(u32, v)));
+    } else {
+        const u64 b = __builtin_bit_cast(u64, v);
+        // readfirstlane returns a signed int: widen through u32, not by sign extension
+        const u64 r = ((u64)(u32)__builtin_amdgcn_readfirstlane((u32)(b >> 32)) << 32) |
+                      (u64)(u32)__builtin_amdgcn_readfirstlane((u32)b);
+        return __builtin_bit_cast(V, r);
+    }
+}
+
 __device__ __forceinline__ u32 rank_in(u64 mask)
 {
     return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
@@ -592,7 +607,8 @@ struct DrawIO {
 //   done   consumer -> producer: (e << 24) | low 24 bits of the first draw the
 //          consumer has not read yet;
 //   made   producer -> consumer: (e << 24) | low 24 bits of the first draw not
-//          made yet; draws [made - D, made) of epoch e are in the ring.
+//          made yet; draws [made - D, made) of epoch e are in the ring (the
+//          consumer resets it at a claim, before publishing the epoch).
 // The producer writes draw p only while p < done + D, so a draw the consumer
 // finds made stays in place until it has read it. Ordering rests on waits for
 // completed LDS operations (lgkmcnt 0): the producer waits for its ring
@@ -638,11 +654,16 @@ struct RingFeed {
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
 
-    // a new trajectory on this lane; the loop forms draws n and n + 1 itself
+    // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
+    // made is reset to "nothing made in this epoch" before the epoch is
+    // published, so a made word the lane finds in its epoch was written for it
+    // (a late write from an older epoch is a few epochs behind, never a hit)
     __device__ void claim(u32 id, u64 n)
     {
         eb = eb % 255u + 1u;
-        lds_st(&ctl->done[lane], (eb << 24) | ((u32)(n + 1) & 0xFFFFFFu));
+        const u32 w = (eb << 24) | ((u32)(n + 1) & 0xFFFFFFu);
+        lds_st(&ctl->done[lane], w);
+        lds_st(&ctl->made[lane], w);
         lds_st(&ctl->req_id[lane], id);
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
@@ -661,16 +682,19 @@ struct RingFeed {
         DrawIO<P, NSLOT>::load(ring + ((u32)want & (u32)(D - 1)) * (NWMAX * 64) + lane, d);
     }
 
-    // where the ring did not hold draw `want` of this trajectory, form it here
+    // where the ring did not hold draw `want` of this trajectory, form it here.
+    // made and (eb, want) as words differ by 1..D exactly when the epochs match
+    // and want < made <= want + D: a made word of another epoch is at least 2^24
+    // - 2^23 away (epochs only grow, and the low 24 bits of an event index move
+    // by less than 2^23 within an epoch's reach of the ring)
     template <class P, int NSLOT, int SLOT_LOG>
     __device__ void finish(Draw<P, NSLOT> &d, u32 mw, u64 want, u32 id, u64 act, u32 k0, u32 k1) const
     {
-        const bool e_ok = (mw >> 24) == eb;
-        const bool r_ok = ((mw - (u32)want) & 0xFFFFFFu) - 1u < (u32)D;   // want < made <= want + D
-        if (__builtin_expect((act & ~(lanes(e_ok) & lanes(r_ok))) != 0, 0)) {
+        const bool hit = mw - ((eb << 24) | ((u32)want & 0xFFFFFFu)) - 1u < (u32)D;
+        if (__builtin_expect((act & ~lanes(hit)) != 0, 0)) {
             __asm__ volatile("");
             const Draw<P, NSLOT> s = make_draw<P, NSLOT, SLOT_LOG>(want, id, k0, k1);
-            if (!(e_ok && r_ok))
+            if (!hit)
                 d = s;
         }
     }
@@ -694,15 +718,13 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
         const u32 re = lds_ld(&ctl->req_e[lane]);
         lgkm_wait();   // a new epoch's request words were written before it
         const u32 item = __builtin_amdgcn_readfirstlane(lds_ld(&ctl->item));
-        const u32 rid = lds_ld(&ctl->req_id[lane]);
-        const u32 rlo = lds_ld(&ctl->req_lo[lane]), rhi = lds_ld(&ctl->req_hi[lane]);
         const u32 dw = lds_ld(&ctl->done[lane]);
         if (item != seq)
             break;
         if (re != e) {
             e = re;
-            id = rid;
-            p = (((u64)rhi << 32) | rlo) + 1;
+            id = lds_ld(&ctl->req_id[lane]);
+            p = (((u64)lds_ld(&ctl->req_hi[lane]) << 32) | lds_ld(&ctl->req_lo[lane])) + 1;
         }
         const u32 ahead = ((u32)p - dw) & 0xFFFFFFu;   // draws made and not yet read
         const u32 room = (e != 0 && (dw >> 24) == e && ahead < (u32)D) ? (u32)D - ahead : 0u;
@@ -790,9 +812,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
     bool open = true;
 
     if constexpr (!PER_LANE_RATES) {
+        // one set for the item: wave-uniform, kept in scalar registers
 #pragma unroll
         for (int j = 0; j < M; ++j)
-            c[j] = rates[j];
+            c[j] = uniform_value(rates[j]);
     }
 
     for (;;) {
@@ -892,11 +915,13 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 // type the exact version runs and no conversion stream is drawn.
                 T a[M];
                 if constexpr (P::SR && !P::SELECTIVE && Md::NCONV > 0) {
-                    i32 mx = x[0] < 0 ? -x[0] : x[0];
+                    // counts are never negative; as unsigned, a negative one would
+                    // only send the wave to the version that handles every count
+                    u32 mx = (u32)x[0];
 #pragma unroll
                     for (int s = 1; s < N; ++s)
-                        mx = (x[s] < 0 ? -x[s] : x[s]) > mx ? (x[s] < 0 ? -x[s] : x[s]) : mx;
-                    if (__builtin_expect((act & lanes(mx > P::EXACT_INT)) == 0, 1)) {
+                        mx = (u32)x[s] > mx ? (u32)x[s] : mx;
+                    if (__builtin_expect((act & lanes(mx > (u32)P::EXACT_INT)) == 0, 1)) {
                         Md::template propensities<P, true>(x, c, hill, a, pool, NoConv());
                     } else {
                         // the empty asm keeps this a branch: merged with the exact
@@ -987,7 +1012,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 // ---- integer update (mu = M: nothing fires)
                 Md::update(x, fire ? mu : M);
                 t = fire ? t_new : t;
-                n += fire ? 1u : 0u;
+                n = want;   // also where the event does not fire: such a lane stops, and is reset below
                 if constexpr (Md::REC != 0) {
                     // event record: firings of the recorded reactions, with the clock after them
                     if (fire && ((Md::REC >> mu) & 1ull)) {
@@ -1004,6 +1029,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
             } while (__builtin_expect(stop_lanes == 0, 1));
             if (active && (!fire || n == n_stop)) {
+                if (!fire)
+                    n -= 1;
                 // ---- finish (or suspend) this trajectory, once per trajectory
                 int status;
                 if (!a_ok)
