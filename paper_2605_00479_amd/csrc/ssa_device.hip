@@ -702,15 +702,15 @@ struct RingFeed {
 
 // Producer wave of one item: for each lane, the draws of its consumer lane's
 // trajectory from the claim's event index + 1 on, up to D ahead of the
-// consumer, formed in batches of up to four independent draws (their Philox
-// and logarithm chains overlap). Returns once the consumer has moved past
-// item `seq`.
+// consumer, formed in batches of up to eight independent draws (their Philox
+// and logarithm chains overlap, and the polling is paid once per batch).
+// Returns once the consumer has moved past item `seq`.
 template <class P, class Md, int D, int NWMAX>
 __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ctl, u32 *ring, u32 seq)
 {
     typedef Slots<P, Md> S;
     typedef DrawIO<P, S::NSLOT> IO;
-    constexpr int BATCH = D < 4 ? D : 4;
+    constexpr int BATCH = D < 8 ? D : 8;
     const u32 lane = lane_id();
     u32 e = 0, id = 0;
     u64 p = 0;
@@ -726,8 +726,16 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
             id = lds_ld(&ctl->req_id[lane]);
             p = (((u64)lds_ld(&ctl->req_hi[lane]) << 32) | lds_ld(&ctl->req_lo[lane])) + 1;
         }
-        const u32 ahead = ((u32)p - dw) & 0xFFFFFFu;   // draws made and not yet read
-        const u32 room = (e != 0 && (dw >> 24) == e && ahead < (u32)D) ? (u32)D - ahead : 0u;
+        // draws made and not yet read: p - done, as a signed 24-bit difference. The
+        // event-loop lane may be ahead (it forms draws itself until the ring holds
+        // them, e.g. right after a claim): then skip to its next unread draw.
+        const bool mine = e != 0 && (dw >> 24) == e;
+        i32 ahead = (i32)(((u32)p - dw) << 8) >> 8;
+        if (mine && ahead < 0) {
+            p += (u64)(u32)(-ahead);
+            ahead = 0;
+        }
+        const u32 room = (mine && ahead < D) ? (u32)(D - ahead) : 0u;
         if (__builtin_amdgcn_ballot_w64(room != 0u) == 0) {
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -750,13 +758,13 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
     (void)I;
 }
 
-// Ring depth for draws of nw words: the largest power of two up to 8 whose
-// four rings fit 56 KiB of LDS; 0 where not even a depth of 2 fits (then the
+// Ring depth for draws of nw words: the largest power of two up to 16 whose
+// four rings fit 88 KiB of LDS; 0 where not even a depth of 2 fits (then the
 // 512-thread kernel runs eight event-loop waves that form their own draws).
 __host__ __device__ constexpr int ring_depth(int nw)
 {
-    int d = 8;
-    while (d >= 2 && 4 * d * nw * 64 * 4 > 57344)
+    int d = 16;
+    while (d >= 2 && 4 * d * nw * 64 * 4 > 90112)
         d /= 2;
     return d >= 2 ? d : 0;
 }
