@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with FMA contraction off (binary32/64 ops stay
     single correctly rounded IEEE operations)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", *_arch_flags(),
                "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra", "-Wno-maybe-uninitialized", "-o", _LIB, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
@@ -69,14 +69,28 @@ class _Run(ctypes.Structure):
 _lib = None
 
 
+def _arch_flags():
+    """-mfma where the host has FMA3, so the explicit fma()/fmaf() calls of the
+    logarithm are single instructions (the same correctly rounded operation as
+    libm's, which emulates it otherwise); contraction stays off."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("flags") and " fma " in line + " ":
+                    return ["-mfma"]
+    except OSError:
+        pass
+    return []
+
+
 def build_variant(src_text: str, out_path: str) -> str:
     """Compile oracle source text (e.g. a deliberately altered copy used by the
     tests that check the pins catch mistakes) into out_path."""
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
-    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
-                    "-fPIC", "-w", "-o", out_path, src, "-lm"], check=True)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", *_arch_flags(), "-fopenmp",
+                    "-shared", "-fPIC", "-w", "-o", out_path, src, "-lm"], check=True)
     return out_path
 
 

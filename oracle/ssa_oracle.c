@@ -109,6 +109,11 @@ float or_u24(uint32_t w)
 /* u = 2^e * f with f in [1/sqrt2, sqrt2]; ln u = e ln2 + ln f;               */
 /* ln f = 2 atanh(s), s = (f-1)/(f+1): 2s (1 + s^2/3 + s^4/5 + ...).          */
 /* ln 2 is split (Cody & Waite) so that e*LN2_HI is exact.                    */
+/* The paper does not fix the logarithm; this is the project's definition,   */
+/* with every step a correctly rounded IEEE operation: s is the correctly    */
+/* rounded quotient, the series is evaluated by Horner's rule with fused     */
+/* multiply-adds (one rounding per step), ln f = fma(2s, p z, 2s), and       */
+/* r = fma(e, LN2_HI, fma(e, LN2_LO, ln f)) (e * LN2_HI is exact).            */
 /* ------------------------------------------------------------------------- */
 static const double LN2_HI_D = 0x1.62e42fep-1;         /* ln 2 truncated to 29 bits */
 static const double LN2_LO_D = 0x1.f473de6af278fp-30;  /* ln 2 - LN2_HI_D */
@@ -136,12 +141,12 @@ double or_nlog64(double u)
     double z = s * s;
     double p = ATANH_D[9];
     for (int i = 8; i >= 0; --i)
-        p = p * z + ATANH_D[i];
+        p = fma(p, z, ATANH_D[i]);
     p = p * z;
     double s2 = s + s;
-    double lnf = s2 + s2 * p;
+    double lnf = fma(s2, p, s2);
     double ed = (double)e;
-    double r = ed * LN2_HI_D + (ed * LN2_LO_D + lnf);
+    double r = fma(ed, LN2_HI_D, fma(ed, LN2_LO_D, lnf));
     return 0.0 - r;
 }
 
@@ -167,12 +172,12 @@ float or_nlog32(float u)
     float z = s * s;
     float p = ATANH_F[3];
     for (int i = 2; i >= 0; --i)
-        p = p * z + ATANH_F[i];
+        p = fmaf(p, z, ATANH_F[i]);
     p = p * z;
     float s2 = s + s;
-    float lnf = s2 + s2 * p;
+    float lnf = fmaf(s2, p, s2);
     float ed = (float)e;
-    float r = ed * LN2_HI_F + (ed * LN2_LO_F + lnf);
+    float r = fmaf(ed, LN2_HI_F, fmaf(ed, LN2_LO_F, lnf));
     return 0.0f - r;
 }
 

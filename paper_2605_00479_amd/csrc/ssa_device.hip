@@ -109,7 +109,9 @@ __device__ __forceinline__ float div_rn_inrange(float a, float b)
 // -ln(u), u in (0, 1]: u = 2^e f with f in [1/sqrt2, sqrt2],
 // ln f = 2 atanh(s) = 2s (1 + s^2/3 + s^4/5 + ...), s = (f - 1)/(f + 1),
 // e ln2 with ln2 split in a short high part (exact product) and a low part.
-// Only correctly rounded +, -, *, / are used, in a fixed order.
+// Only correctly rounded +, -, *, / and fused multiply-adds are used, in a
+// fixed order: the quotient s, the series by Horner's rule in fmas, ln f =
+// fma(2s, p z, 2s), and fma(e, ln2_hi, fma(e, ln2_lo, ln f)).
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double neg_log64(double u)
 {
@@ -122,21 +124,21 @@ __device__ __forceinline__ double neg_log64(double u)
     }
     double s = (f - 1.0) / (f + 1.0);
     double z = s * s;
-    double p = 0x1.8618618618618p-5;          // 1/21
-    p = p * z + 0x1.af286bca1af28p-5;         // 1/19
-    p = p * z + 0x1.e1e1e1e1e1e1ep-5;         // 1/17
-    p = p * z + 0x1.1111111111111p-4;         // 1/15
-    p = p * z + 0x1.3b13b13b13b14p-4;         // 1/13
-    p = p * z + 0x1.745d1745d1746p-4;         // 1/11
-    p = p * z + 0x1.c71c71c71c71cp-4;         // 1/9
-    p = p * z + 0x1.2492492492492p-3;         // 1/7
-    p = p * z + 0x1.999999999999ap-3;         // 1/5
-    p = p * z + 0x1.5555555555555p-2;         // 1/3
+    double p = 0x1.8618618618618p-5;         // 1/21
+    p = __builtin_fma(p, z, 0x1.af286bca1af28p-5); // 1/19
+    p = __builtin_fma(p, z, 0x1.e1e1e1e1e1e1ep-5); // 1/17
+    p = __builtin_fma(p, z, 0x1.1111111111111p-4); // 1/15
+    p = __builtin_fma(p, z, 0x1.3b13b13b13b14p-4); // 1/13
+    p = __builtin_fma(p, z, 0x1.745d1745d1746p-4); // 1/11
+    p = __builtin_fma(p, z, 0x1.c71c71c71c71cp-4); // 1/9
+    p = __builtin_fma(p, z, 0x1.2492492492492p-3); // 1/7
+    p = __builtin_fma(p, z, 0x1.999999999999ap-3); // 1/5
+    p = __builtin_fma(p, z, 0x1.5555555555555p-2); // 1/3
     p = p * z;
     double s2 = s + s;
-    double lnf = s2 + s2 * p;
+    double lnf = __builtin_fma(s2, p, s2);
     double ed = (double)e;
-    double r = ed * 0x1.62e42fep-1 + (ed * 0x1.f473de6af278fp-30 + lnf);
+    double r = __builtin_fma(ed, 0x1.62e42fep-1, __builtin_fma(ed, 0x1.f473de6af278fp-30, lnf));
     return 0.0 - r;
 }
 
@@ -152,14 +154,14 @@ __device__ __forceinline__ float neg_log32(float u)
     float s = div_rn_inrange(f - 1.0f, f + 1.0f);   // |f - 1| < 0.42, f + 1 in [1.7, 2.5)
     float z = s * s;
     float p = 0x1.c71c72p-4f;                 // 1/9
-    p = p * z + 0x1.24924ap-3f;               // 1/7
-    p = p * z + 0x1.99999ap-3f;               // 1/5
-    p = p * z + 0x1.555556p-2f;               // 1/3
+    p = __builtin_fmaf(p, z, 0x1.24924ap-3f); // 1/7
+    p = __builtin_fmaf(p, z, 0x1.99999ap-3f); // 1/5
+    p = __builtin_fmaf(p, z, 0x1.555556p-2f); // 1/3
     p = p * z;
     float s2 = s + s;
-    float lnf = s2 + s2 * p;
+    float lnf = __builtin_fmaf(s2, p, s2);
     float ed = (float)e;
-    float r = ed * 0x1.62e4p-1f + (ed * 0x1.7f7d1cp-20f + lnf);
+    float r = __builtin_fmaf(ed, 0x1.62e4p-1f, __builtin_fmaf(ed, 0x1.7f7d1cp-20f, lnf));
     return 0.0f - r;
 }
 

@@ -154,9 +154,9 @@ MUTATIONS = [
     ("philox low halves swapped", "        uint32_t n1 = lo1;", "        uint32_t n1 = lo0;", kat_fails),
     ("uniform can be zero", "    return (double)(m + 1u) * 0x1p-53;", "    return (double)(m) * 0x1p-53;",
      uniform_range_fails),
-    ("log series sign", "    double lnf = s2 + s2 * p;", "    double lnf = s2 - s2 * p;", log_ulp_fails),
-    ("log drops low part of ln2", "    double r = ed * LN2_HI_D + (ed * LN2_LO_D + lnf);",
-     "    double r = ed * LN2_HI_D + lnf;", log_ulp_fails),
+    ("log series sign", "    double lnf = fma(s2, p, s2);", "    double lnf = fma(-s2, p, s2);", log_ulp_fails),
+    ("log drops low part of ln2", "    double r = fma(ed, LN2_HI_D, fma(ed, LN2_LO_D, lnf));",
+     "    double r = fma(ed, LN2_HI_D, lnf);", log_ulp_fails),
     ("RNE ties away from zero", "(frac == 0.5 && fmod(fl, 2.0) == 1.0)", "(frac == 0.5)", rne_fails),
     ("SR strict comparison", "        up = rtop + floor(frac * scale) >= scale;",
      "        up = rtop + floor(frac * scale) > scale;", sr_probability_fails),
