@@ -1,0 +1,212 @@
+"""Model check of the draw-ring protocol between an event-loop lane and its
+producer lane (the 512-thread kernel, ssa_kernel_pc).
+
+The two agents are modelled as step machines whose steps are the kernel's LDS
+operations, in the kernel's order and with its 32-bit arithmetic (epoch byte,
+24-bit event indices). A random scheduler interleaves them; a step is atomic
+and the waits the kernel places (lgkmcnt 0) make each agent's steps take effect
+in program order, which is what the model assumes. Each ring slot stores the
+identity (trajectory id, event index) of the draw written to it, so the check is direct:
+whenever the event-loop lane takes a draw from the ring, it must be the draw of
+its current trajectory and event. Runs cover slow and fast producers, short
+trajectories that cycle the 255 epochs many times, event indices crossing the
+24-bit wrap, and a producer that sees claims late (it then skips ahead).
+
+This checks the protocol as designed; the GPU tests check the kernel's results.
+"""
+import random
+
+import pytest
+
+M24 = 0xFFFFFF
+
+
+def s24(v):
+    """Low 24 bits of v as a signed difference (the producer's ((u32)x << 8) >> 8)."""
+    v &= M24
+    return v - (1 << 24) if v & 0x800000 else v
+
+
+class Shared:
+    def __init__(self, D):
+        self.made = 0
+        self.done = 0
+        self.req_e = 0
+        self.req_id = 0
+        self.req_lo = 0
+        self.req_hi = 0
+        self.ring = [None] * D
+
+
+def consumer(sh, D, rng, n_traj, start_n, log, lengths):
+    """Generator: one step per LDS operation (plus the local work between)."""
+    eb = 0
+    for uid in range(1, n_traj + 1):     # uid: the trajectory's id (draws are keyed by it)
+        n = start_n(rng)
+        log["claim_step"] = log["step"]
+        # claim: done = made = (eb, n + 1); request words; wait; epoch
+        eb = eb % 255 + 1
+        w = (eb << 24) | ((n + 1) & M24)
+        sh.done = w
+        yield
+        sh.made = w
+        yield
+        sh.req_id, sh.req_lo, sh.req_hi = uid, n & 0xFFFFFFFF, n >> 32
+        yield
+        sh.req_e = eb
+        yield
+        length = lengths(rng)
+        for _ in range(length):
+            want = n + 1
+            mw = sh.made                                      # top of the event
+            yield
+            sh.done = (eb << 24) | (want & M24)               # after the wait: done, then ring words
+            yield
+            data = sh.ring[want % D]
+            yield
+            hit = ((mw - ((eb << 24) | (want & M24)) - 1) & 0xFFFFFFFF) < D
+            if hit:
+                log["hits"] += 1
+                assert data == (uid, want), f"stale draw: got {data}, wanted {(uid, want)}"
+            else:
+                log["misses"] += 1                            # formed by the lane itself
+            n = want                                          # the event fires
+    log["consumer_done"] = True
+
+
+def producer(sh, D, batch, rng, log, skip=True):
+    e, p, uid = 0, 0, 0
+    while not log.get("consumer_done"):
+        re = sh.req_e
+        yield
+        dw = sh.done                                          # after the wait
+        yield
+        if re != e:
+            e = re
+            uid = sh.req_id
+            p = ((sh.req_hi << 32) | sh.req_lo) + 1
+            yield
+        mine = e != 0 and (dw >> 24) == e
+        if skip:
+            ahead = s24((p & 0xFFFFFFFF) - dw)
+            if mine and ahead < 0:
+                p += -ahead
+                ahead = 0
+        else:   # the unsigned distance without the skip: behind reads as a full ring
+            ahead = ((p & 0xFFFFFFFF) - dw) & M24
+        room = D - ahead if (mine and ahead < D) else 0
+        if room == 0:
+            yield                                             # sleep
+            continue
+        k = min(room, batch)
+        for b in range(k):
+            sh.ring[(p + b) % D] = (uid, p + b)
+            yield
+        sh.made = (e << 24) | ((p + k) & M24)                 # after the wait for the stores
+        yield
+        p += k
+        log["made"] += k
+
+
+def mixed_lengths(r):
+    return r.choice([0, 1, 2, 3, r.randint(4, 60)])
+
+
+def run(seed, D=16, batch=8, p_producer=0.5, n_traj=300, start=None, skip=True, lengths=mixed_lengths,
+        hold_after_claim=0):
+    """hold_after_claim: the producer does not run for that many steps after each
+    claim (it sees the claim late, after the lane has formed draws itself)."""
+    rng = random.Random(seed)
+    sh = Shared(D)
+    log = {"hits": 0, "misses": 0, "made": 0, "step": 0, "claim_step": 0}
+    start = start or (lambda r: r.randint(0, 50))
+    c = consumer(sh, D, rng, n_traj, start, log, lengths)
+    pr = producer(sh, D, batch, rng, log, skip)
+    live = {"c": c, "p": pr}
+    while "c" in live:
+        held = log["step"] - log["claim_step"] < hold_after_claim
+        who = "p" if ("p" in live and not held and rng.random() < p_producer) else "c"
+        log["step"] += 1
+        try:
+            next(live[who])
+        except StopIteration:
+            del live[who]
+    return log
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("p_producer", [0.15, 0.5, 0.85])
+def test_ring_hits_are_always_the_wanted_draw(seed, p_producer):
+    log = run(seed, p_producer=p_producer)     # the stale-draw check is inside
+    if p_producer >= 0.5:
+        assert log["hits"] > log["misses"]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_epoch_wrap_with_short_trajectories(seed):
+    # 2,000 claims (the 255 epochs cycle about 8 times), mostly trajectories of
+    # 0-3 events, with a producer slow enough to leave made words of old epochs
+    # behind: none may read as a hit for a later epoch with the same byte
+    log = run(100 + seed, p_producer=0.2, n_traj=2000,
+              lengths=lambda r: r.choice([0, 0, 1, 2, 3, r.randint(10, 30)]))
+    assert log["hits"] > 0 and log["misses"] > 0
+
+
+def bursts_of_finished(r, state):
+    """Runs of 254 trajectories without an event (finished trajectories claimed
+    again in a later window stop at once), then a short one with events, so
+    the lane's epoch byte returns to a value its made word may still hold."""
+    state["i"] = state.get("i", 0) + 1
+    return 3 if state["i"] % 255 == 1 else 0
+
+
+def epoch_reuse_run(run_fn, bursts, seed):
+    # every trajectory starts at event 5; the producer sees claims only 10
+    # steps late, so it never sees the empty ones (a claim takes 4 steps)
+    st = {}
+    return run_fn(seed, p_producer=0.5, n_traj=255 * 8 + 1, start=lambda r: 5,
+                  lengths=lambda r: bursts(r, st), hold_after_claim=10)
+
+
+def test_epoch_byte_reuse_after_bursts_of_empty_claims():
+    for seed in range(20):
+        epoch_reuse_run(run, bursts_of_finished, 400 + seed)
+
+
+def test_the_made_reset_at_claim_is_what_prevents_stale_hits():
+    # the same runs against a copy of the model whose claim does not reset
+    # made: a made word left from 255 claims earlier then reads as a hit and
+    # hands the lane another trajectory's draw
+    src = open(__file__).read()
+    variant = src.replace("        sh.made = w\n        yield\n        sh.req_id", "        sh.req_id")
+    assert variant != src
+    ns = {"__name__": "variant"}
+    exec(compile(variant, "variant", "exec"), ns)
+    stale = 0
+    for seed in range(20):
+        try:
+            epoch_reuse_run(ns["run"], ns["bursts_of_finished"], 400 + seed)
+        except AssertionError:
+            stale += 1
+    assert stale > 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_event_index_crosses_the_24_bit_wrap(seed):
+    log = run(200 + seed, start=lambda r: (1 << 24) - r.randint(1, 40), n_traj=200)
+    assert log["hits"] > 0
+
+
+@pytest.mark.parametrize("D,batch", [(2, 2), (4, 4), (8, 4), (16, 8)])
+def test_ring_depths_and_batches(D, batch):
+    for seed in range(3):
+        run(300 + seed, D=D, batch=batch)
+
+
+def test_a_late_producer_skips_ahead_and_keeps_up():
+    # the producer sees each claim only after the lane has formed a few draws
+    # itself; without the skip it stays behind for the rest of the trajectory
+    long_runs = lambda r: r.randint(80, 120)
+    fast = run(7, p_producer=0.5, n_traj=100, lengths=long_runs, hold_after_claim=40)
+    stuck = run(7, p_producer=0.5, n_traj=100, lengths=long_runs, hold_after_claim=40, skip=False)
+    assert fast["hits"] > 5 * max(stuck["hits"], 1)
