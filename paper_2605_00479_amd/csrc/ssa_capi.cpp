@@ -333,7 +333,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
       << "  if (w < 4) {\n"
       << "    __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"
       << "      lgkm_wait();\n"

@@ -550,46 +550,55 @@ struct Slots {
 };
 
 // A draw as 32-bit words: the pool's words, then L and u2 (one word each in
-// binary32, two in binary64). Word k of a stored draw sits at w[64 k], so the
-// 64 lanes of a wave touch 64 consecutive words.
+// binary32, two in binary64). Word k of a stored draw sits at w[S k], with S a
+// multiple of 64, so the 64 lanes of a wave touch 64 consecutive words.
 template <class P, int NSLOT>
 struct DrawIO {
     static constexpr int NP = NSLOT > 0 ? Pool<NSLOT, P::SR_B>::NW : 0;
     static constexpr int NA = (int)(sizeof(typename P::A) / 4);
     static constexpr int NW = NP + 2 * NA;
 
+    template <int S>
     __device__ static void store(u32 *w, const Draw<P, NSLOT> &d)
     {
         if constexpr (NP > 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                w[64 * k] = d.pool.w[k];
+                w[S * k] = d.pool.w[k];
         }
         if constexpr (NA == 1) {
-            w[64 * NP] = __float_as_uint((float)d.L);
-            w[64 * (NP + 1)] = __float_as_uint((float)d.u2);
+            w[S * NP] = __float_as_uint((float)d.L);
+            w[S * (NP + 1)] = __float_as_uint((float)d.u2);
         } else {
             const u64 a = (u64)__double_as_longlong((double)d.L), b = (u64)__double_as_longlong((double)d.u2);
-            w[64 * NP] = (u32)a;
-            w[64 * (NP + 1)] = (u32)(a >> 32);
-            w[64 * (NP + 2)] = (u32)b;
-            w[64 * (NP + 3)] = (u32)(b >> 32);
+            w[S * NP] = (u32)a;
+            w[S * (NP + 1)] = (u32)(a >> 32);
+            w[S * (NP + 2)] = (u32)b;
+            w[S * (NP + 3)] = (u32)(b >> 32);
         }
     }
 
-    __device__ static void load(const u32 *w, Draw<P, NSLOT> &d)
+    // the pool's words (needed first: the propensities' rounding fields)
+    template <int S>
+    __device__ static void load_pool(const u32 *w, Draw<P, NSLOT> &d)
     {
         if constexpr (NP > 0) {
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                d.pool.w[k] = w[64 * k];
+                d.pool.w[k] = w[S * k];
         }
+    }
+
+    // L and u2 (needed later in an event than the pool)
+    template <int S>
+    __device__ static void load_tail(const u32 *w, Draw<P, NSLOT> &d)
+    {
         if constexpr (NA == 1) {
-            d.L = __uint_as_float(w[64 * NP]);
-            d.u2 = __uint_as_float(w[64 * (NP + 1)]);
+            d.L = __uint_as_float(w[S * NP]);
+            d.u2 = __uint_as_float(w[S * (NP + 1)]);
         } else {
-            d.L = __longlong_as_double((long long)(((u64)w[64 * (NP + 1)] << 32) | w[64 * NP]));
-            d.u2 = __longlong_as_double((long long)(((u64)w[64 * (NP + 3)] << 32) | w[64 * (NP + 2)]));
+            d.L = __longlong_as_double((long long)(((u64)w[S * (NP + 1)] << 32) | w[S * NP]));
+            d.u2 = __longlong_as_double((long long)(((u64)w[S * (NP + 3)] << 32) | w[S * (NP + 2)]));
         }
     }
 };
@@ -603,14 +612,16 @@ struct DrawIO {
 // (same function of seed, trajectory and event index), so results do not
 // depend on the feed.
 //
-// Protocol, per lane (consumer lane l and producer lane l of the paired waves):
+// Protocol, per lane (consumer lane l and producer lane l of the paired waves).
+// A counter word is (low 24 bits of an event index) << 8 | epoch, so a lane
+// steps it by adding 256 and the 24-bit index wraps without touching the epoch:
 //   req_*  consumer -> producer: trajectory id and claim event index, then the
 //          epoch e (1..255, new at every claim) once the rest is written;
-//   done   consumer -> producer: (e << 24) | low 24 bits of the first draw the
-//          consumer has not read yet;
-//   made   producer -> consumer: (e << 24) | low 24 bits of the first draw not
-//          made yet; draws [made - D, made) of epoch e are in the ring (the
-//          consumer resets it at a claim, before publishing the epoch).
+//   done   consumer -> producer: counter word of the first draw the consumer
+//          has not read yet;
+//   made   producer -> consumer: counter word of the first draw not made yet;
+//          draws [made - D, made) of epoch e are in the ring (the consumer
+//          resets it at a claim, before publishing the epoch).
 // The producer writes draw p only while p < done + D, so a draw the consumer
 // finds made stays in place until it has read it. Ordering rests on waits for
 // completed LDS operations (lgkmcnt 0): the producer waits for its ring
@@ -651,10 +662,12 @@ struct SelfFeed {
 template <int D, int NWMAX>
 struct RingFeed {
     static constexpr bool RING = true;
+    static_assert((D & (D - 1)) == 0, "ring depth is a power of two");
     RingCtl *ctl;   // this consumer wave's control words
-    u32 *ring;      // [D][NWMAX][64]
+    u32 *ring;      // [NWMAX][D][64]: word k of slot s, lane l at ring[(k D + s) 64 + l]
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
+    u32 dw;         // counter word of the draw the lane takes next (event n + 1)
 
     // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
     // made is reset to "nothing made in this epoch" before the epoch is
@@ -663,9 +676,9 @@ struct RingFeed {
     __device__ void claim(u32 id, u64 n)
     {
         eb = eb % 255u + 1u;
-        const u32 w = (eb << 24) | ((u32)(n + 1) & 0xFFFFFFu);
-        lds_st(&ctl->done[lane], w);
-        lds_st(&ctl->made[lane], w);
+        dw = ((u32)(n + 1) << 8) | eb;
+        lds_st(&ctl->done[lane], dw);
+        lds_st(&ctl->made[lane], dw);
         lds_st(&ctl->req_id[lane], id);
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
@@ -675,30 +688,48 @@ struct RingFeed {
 
     __device__ u32 made_word() const { return lds_ld(&ctl->made[lane]); }
 
-    // ring words of draw `want` (valid where finish finds the draw made)
-    template <class P, int NSLOT>
-    __device__ void read(u64 want, Draw<P, NSLOT> &d) const
+    // slot of the draw with counter word dw: its index mod D, times the 256
+    // bytes of a slot's word, is dw's index bits [8, 8 + log2 D) in place
+    __device__ const u32 *slot() const
     {
-        lgkm_wait();   // the made word, and the previous draw's ring words, are in
-        lds_st(&ctl->done[lane], (eb << 24) | ((u32)want & 0xFFFFFFu));
-        DrawIO<P, NSLOT>::load(ring + ((u32)want & (u32)(D - 1)) * (NWMAX * 64) + lane, d);
+        return (const u32 *)((const char *)(ring + lane) + (dw & (u32)((D - 1) << 8)));
     }
 
-    // where the ring did not hold draw `want` of this trajectory, form it here.
-    // made and (eb, want) as words differ by 1..D exactly when the epochs match
-    // and want < made <= want + D: a made word of another epoch is at least 2^24
-    // - 2^23 away (epochs only grow, and the low 24 bits of an event index move
-    // by less than 2^23 within an epoch's reach of the ring)
-    template <class P, int NSLOT, int SLOT_LOG>
-    __device__ void finish(Draw<P, NSLOT> &d, u32 mw, u64 want, u32 id, u64 act, u32 k0, u32 k1) const
+    // the pool words of the next draw (valid where finish finds it made)
+    template <class P, int NSLOT>
+    __device__ void read(Draw<P, NSLOT> &d) const
     {
-        const bool hit = mw - ((eb << 24) | ((u32)want & 0xFFFFFFu)) - 1u < (u32)D;
-        if (__builtin_expect((act & ~lanes(hit)) != 0, 0)) {
+        lgkm_wait();   // the made word, and the previous draw's ring words, are in
+        lds_st(&ctl->done[lane], dw);
+        DrawIO<P, NSLOT>::template load_pool<D * 64>(slot(), d);
+    }
+
+    // its L and u2, loaded once this event's are no longer needed
+    template <class P, int NSLOT>
+    __device__ void read_tail(Draw<P, NSLOT> &d) const
+    {
+        DrawIO<P, NSLOT>::template load_tail<D * 64>(slot(), d);
+    }
+
+    // where the ring did not hold the next draw of this trajectory, form it
+    // here; then step to the draw after it. With x = made - (dw + 256), the
+    // draw is made (want < made <= want + D, epochs equal) exactly when x
+    // rotated right by 8 is below D: equal epochs leave a zero low byte and the
+    // index difference minus one above it; any other epoch puts a nonzero byte
+    // on top after the rotation
+    template <class P, int NSLOT, int SLOT_LOG>
+    __device__ void finish(Draw<P, NSLOT> &d, u32 mw, u64 want, u32 id, u64 act, u32 k0, u32 k1)
+    {
+        const u32 next = dw + 256u;
+        const bool hit = __builtin_amdgcn_alignbit(mw - next, mw - next, 8) < (u32)D;
+        const u64 miss = act & ~lanes(hit);
+        if (__builtin_expect(miss != 0, 0)) {
             __asm__ volatile("");
             const Draw<P, NSLOT> s = make_draw<P, NSLOT, SLOT_LOG>(want, id, k0, k1);
-            if (!hit)
+            if ((miss >> lane) & 1u)
                 d = s;
         }
+        dw = next;
     }
 };
 
@@ -731,8 +762,8 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
         // draws made and not yet read: p - done, as a signed 24-bit difference. The
         // event-loop lane may be ahead (it forms draws itself until the ring holds
         // them, e.g. right after a claim): then skip to its next unread draw.
-        const bool mine = e != 0 && (dw >> 24) == e;
-        i32 ahead = (i32)(((u32)p - dw) << 8) >> 8;
+        const bool mine = e != 0 && (dw & 0xFFu) == e;
+        i32 ahead = (i32)(((u32)p << 8) - (dw & ~0xFFu)) >> 8;
         if (mine && ahead < 0) {
             p += (u64)(u32)(-ahead);
             ahead = 0;
@@ -749,11 +780,11 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
             if ((u32)b < room)
-                IO::store(ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * (NWMAX * 64) + lane, d[b]);
+                IO::template store<D * 64>(ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * 64 + lane, d[b]);
         const u32 k = room < (u32)BATCH ? room : (u32)BATCH;
         lgkm_wait();
         if (k != 0u) {
-            lds_st(&ctl->made[lane], (e << 24) | ((u32)(p + k) & 0xFFFFFFu));
+            lds_st(&ctl->made[lane], ((u32)(p + k) << 8) | e);
             p += k;
         }
     }
@@ -911,13 +942,12 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 // ---- draws: cur belongs to event n; event n+1's is formed (or
                 // taken from the producer's ring) alongside
                 const u32 id = I.id_base + idx;
-                const u64 want = n + 1;
                 Draw<P, NSLOT> nxt;
                 u32 made_w = 0;
                 if constexpr (F::RING)
                     made_w = feed.made_word();
                 else
-                    nxt = make_draw<P, NSLOT, SLOT_LOG>(want, id, L.seed_lo, L.seed_hi);
+                    nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
                 const Pool<NSLOT, P::SR_B> &pool = cur.pool;
                 // ---- propensities (generated op sequence). Conversions of
                 // counts draw random bits only when they round: when every
@@ -945,7 +975,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                     Md::template propensities<P, false>(x, c, hill, a, pool, NoConv());
                 }
                 if constexpr (F::RING)
-                    feed.read(want, nxt);
+                    feed.read(nxt);
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
                 m_ok = true;
@@ -1005,6 +1035,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                     target = P::arnd(f32_kept(cur.u2 * a0), pool.hw(SLOT_TARGET));
                 else
                     target = cur.u2 * a0;
+                if constexpr (F::RING)
+                    feed.read_tail(nxt);   // cur's L and u2 are used by now
                 int mu = 0;
 #pragma unroll
                 for (int j = 0; j < M; ++j)
@@ -1022,7 +1054,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 // ---- integer update (mu = M: nothing fires)
                 Md::update(x, fire ? mu : M);
                 t = fire ? t_new : t;
-                n = want;   // also where the event does not fire: such a lane stops, and is reset below
+                n += 1;   // also where the event does not fire: such a lane stops, and is reset below
                 if constexpr (Md::REC != 0) {
                     // event record: firings of the recorded reactions, with the clock after them
                     if (fire && ((Md::REC >> mu) & 1ull)) {
@@ -1034,7 +1066,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                     }
                 }
                 if constexpr (F::RING)
-                    feed.template finish<P, NSLOT, SLOT_LOG>(nxt, made_w, want, id, act, L.seed_lo, L.seed_hi);
+                    feed.template finish<P, NSLOT, SLOT_LOG>(nxt, made_w, n, id, act, L.seed_lo, L.seed_hi);
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
                 stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
             } while (__builtin_expect(stop_lanes == 0, 1));

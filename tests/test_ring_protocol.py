@@ -2,8 +2,8 @@
 producer lane (the 512-thread kernel, ssa_kernel_pc).
 
 The two agents are modelled as step machines whose steps are the kernel's LDS
-operations, in the kernel's order and with its 32-bit arithmetic (epoch byte,
-24-bit event indices). A random scheduler interleaves them; a step is atomic
+operations, in the kernel's order and with its 32-bit arithmetic: a counter
+word is (low 24 bits of an event index) << 8 | epoch byte. A random scheduler interleaves them; a step is atomic
 and the waits the kernel places (lgkmcnt 0) make each agent's steps take effect
 in program order, which is what the model assumes. Each ring slot stores the
 identity (trajectory id, event index) of the draw written to it, so the check is direct:
@@ -18,13 +18,23 @@ import random
 
 import pytest
 
-M24 = 0xFFFFFF
+M32 = 0xFFFFFFFF
 
 
-def s24(v):
-    """Low 24 bits of v as a signed difference (the producer's ((u32)x << 8) >> 8)."""
-    v &= M24
-    return v - (1 << 24) if v & 0x800000 else v
+def word(idx, e):
+    """Counter word of event index idx in epoch e."""
+    return ((idx << 8) | e) & M32
+
+
+def sra8(v):
+    """(i32)v >> 8: arithmetic shift of a 32-bit word."""
+    v &= M32
+    return (v - (1 << 32) if v & 0x80000000 else v) >> 8
+
+
+def rotr8(v):
+    v &= M32
+    return ((v >> 8) | (v << 24)) & M32
 
 
 class Shared:
@@ -44,12 +54,12 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths):
     for uid in range(1, n_traj + 1):     # uid: the trajectory's id (draws are keyed by it)
         n = start_n(rng)
         log["claim_step"] = log["step"]
-        # claim: done = made = (eb, n + 1); request words; wait; epoch
+        # claim: done = made = word(n + 1); request words; wait; epoch
         eb = eb % 255 + 1
-        w = (eb << 24) | ((n + 1) & M24)
-        sh.done = w
+        dw = word(n + 1, eb)
+        sh.done = dw
         yield
-        sh.made = w
+        sh.made = dw
         yield
         sh.req_id, sh.req_lo, sh.req_hi = uid, n & 0xFFFFFFFF, n >> 32
         yield
@@ -60,11 +70,13 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths):
             want = n + 1
             mw = sh.made                                      # top of the event
             yield
-            sh.done = (eb << 24) | (want & M24)               # after the wait: done, then ring words
+            sh.done = dw                                      # after the wait: done, then ring words
             yield
-            data = sh.ring[want % D]
+            data = sh.ring[(dw >> 8) % D]
             yield
-            hit = ((mw - ((eb << 24) | (want & M24)) - 1) & 0xFFFFFFFF) < D
+            nxt = (dw + 256) & M32
+            hit = rotr8(mw - nxt) < D
+            dw = nxt
             if hit:
                 log["hits"] += 1
                 assert data == (uid, want), f"stale draw: got {data}, wanted {(uid, want)}"
@@ -86,14 +98,14 @@ def producer(sh, D, batch, rng, log, skip=True):
             uid = sh.req_id
             p = ((sh.req_hi << 32) | sh.req_lo) + 1
             yield
-        mine = e != 0 and (dw >> 24) == e
+        mine = e != 0 and (dw & 0xFF) == e
         if skip:
-            ahead = s24((p & 0xFFFFFFFF) - dw)
+            ahead = sra8((p << 8) - (dw & ~0xFF))
             if mine and ahead < 0:
                 p += -ahead
                 ahead = 0
         else:   # the unsigned distance without the skip: behind reads as a full ring
-            ahead = ((p & 0xFFFFFFFF) - dw) & M24
+            ahead = (((p << 8) - (dw & ~0xFF)) & M32) >> 8
         room = D - ahead if (mine and ahead < D) else 0
         if room == 0:
             yield                                             # sleep
@@ -102,7 +114,7 @@ def producer(sh, D, batch, rng, log, skip=True):
         for b in range(k):
             sh.ring[(p + b) % D] = (uid, p + b)
             yield
-        sh.made = (e << 24) | ((p + k) & M24)                 # after the wait for the stores
+        sh.made = word(p + k, e)                              # after the wait for the stores
         yield
         p += k
         log["made"] += k
@@ -178,7 +190,7 @@ def test_the_made_reset_at_claim_is_what_prevents_stale_hits():
     # made: a made word left from 255 claims earlier then reads as a hit and
     # hands the lane another trajectory's draw
     src = open(__file__).read()
-    variant = src.replace("        sh.made = w\n        yield\n        sh.req_id", "        sh.req_id")
+    variant = src.replace("        sh.made = dw\n        yield\n        sh.req_id", "        sh.req_id")
     assert variant != src
     ns = {"__name__": "variant"}
     exec(compile(variant, "variant", "exec"), ns)
