@@ -155,12 +155,41 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
         nprop += reaction_main_slots(md, j);
         nconv += reaction_conv_slots(md, j);
     }
+    // lo[s]: the largest order of species s in a mass-action reactant list.
+    // With every count at or above it, no mass-action propensity needs its
+    // zero guard (a count below the order makes the falling factorial zero).
+    std::vector<int> lo((size_t)md.N, 0);
+    for (int j = 0; j < md.M; ++j)
+        if (md.law[j].kind == SSA_LAW_MASS_ACTION)
+            for (int s = 0; s < md.N; ++s)
+                lo[(size_t)s] = std::max(lo[(size_t)s], md.order[(size_t)j * md.N + s]);
+    int lo_max = 0;
+    for (int s = 0; s < md.N; ++s)
+        lo_max = std::max(lo_max, lo[(size_t)s]);
     std::ostringstream o;
     o << "struct Md" << idx << " {\n"
       << "  static constexpr int N = " << md.N << ", M = " << md.M << ", NPROP = " << nprop << ", NCONV = " << nconv
       << ";\n"
       << "  static constexpr u64 REC = " << record_mask << "ull;  // reactions whose firings are recorded\n"
-      << "  template <class P, bool EXACT, class PoolT, class CPoolT>\n"
+      << "  static constexpr int LO_MAX = " << lo_max << ";  // largest reactant order of a species\n"
+      << "  // some count below its species' largest reactant order (a zero guard may apply)\n"
+      << "  __device__ static __forceinline__ bool below(const i32 (&x)[N]) {\n"
+      << "    (void)x;\n"
+      << "    return false";
+    for (int s = 0; s < md.N; ++s)
+        if (lo[(size_t)s] > 0)
+            o << " || x[" << s << "] < " << lo[(size_t)s];
+    o << ";\n  }\n"
+      << "  // max over species of count - largest order, as unsigned (a count below\n"
+      << "  // its order wraps to a large value)\n"
+      << "  __device__ static __forceinline__ u32 range_key(const i32 (&x)[N]) {\n"
+      << "    u32 r = (u32)(x[0] - " << lo[0] << ");\n";
+    for (int s = 1; s < md.N; ++s)
+        o << "    r = (u32)(x[" << s << "] - " << lo[(size_t)s] << ") > r ? (u32)(x[" << s << "] - " << lo[(size_t)s]
+          << ") : r;\n";
+    o << "    return r;\n  }\n"
+      << "  // GUARD = false: every count is at or above its species' largest order\n"
+      << "  template <class P, bool EXACT, bool GUARD, class PoolT, class CPoolT>\n"
       << "  __device__ static __forceinline__ void propensities(const i32 (&x)[N], const typename P::T (&c)[M],"
       << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool, const CPoolT &cpool) {\n"
       << "    typedef typename P::T T;\n"
@@ -189,7 +218,7 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
                     zero += "x[" + std::to_string(s) + "] < " + std::to_string(os);
                 }
             }
-            o << "      a[" << j << "] = (" << zero << ") ? (T)0 : acc; }\n";
+            o << "      a[" << j << "] = (GUARD && (" << zero << ")) ? (T)0 : acc; }\n";
         } else {
             int b = slot;
             o << "    { T xr = P::template cvt<EXACT>(x[" << L.regulator << "], cpool.hw(" << cslot++ << "));\n"

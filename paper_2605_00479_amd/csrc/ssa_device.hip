@@ -735,15 +735,19 @@ struct RingFeed {
 
 // Producer wave of one item: for each lane, the draws of its consumer lane's
 // trajectory from the claim's event index + 1 on, up to D ahead of the
-// consumer, formed in batches of up to eight independent draws (their Philox
-// and logarithm chains overlap, and the polling is paid once per batch).
+// consumer. A batch starts once some lane has START free slots; its BATCH
+// draws are formed in one block, so their Philox and logarithm chains overlap
+// (a lane with fewer free slots stores only those). The shape is measured:
+// with the event loop and this wave sharing a SIMD, 6 draws from 6 free slots
+// of 16 keep the ring ahead for binary32 and 16-bit draws, 8 from 4 for binary64.
 // Returns once the consumer has moved past item `seq`.
 template <class P, class Md, int D, int NWMAX>
 __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ctl, u32 *ring, u32 seq)
 {
     typedef Slots<P, Md> S;
     typedef DrawIO<P, S::NSLOT> IO;
-    constexpr int BATCH = D < 8 ? D : 8;
+    constexpr int BATCH = D >= 16 ? (P::WIDE ? 8 : 6) : (D >= 2 ? D / 2 : 1);
+    constexpr int START = P::WIDE && BATCH > 4 ? 4 : BATCH;
     const u32 lane = lane_id();
     u32 e = 0, id = 0;
     u64 p = 0;
@@ -769,7 +773,7 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
             ahead = 0;
         }
         const u32 room = (mine && ahead < D) ? (u32)(D - ahead) : 0u;
-        if (__builtin_amdgcn_ballot_w64(room != 0u) == 0) {
+        if (__builtin_amdgcn_ballot_w64(room >= (u32)START) == 0) {
             __builtin_amdgcn_s_sleep(2);
             continue;
         }
@@ -777,6 +781,17 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
             d[b] = make_draw<P, S::NSLOT, S::LOG>(p + (u64)b, id, L.seed_lo, L.seed_hi);
+        // formed here, every one: left to the guarded stores below, each
+        // would be formed in a block of its own, one chain after another
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            __asm__ volatile("" : "+v"(d[b].L), "+v"(d[b].u2));
+            if constexpr (S::NSLOT > 0) {
+#pragma unroll
+                for (int k = 0; k < IO::NP; ++k)
+                    __asm__ volatile("" : "+v"(d[b].pool.w[k]));
+            }
+        }
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
             if ((u32)b < room)
@@ -953,26 +968,40 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 // counts draw random bits only when they round: when every
                 // count of every lane is exactly representable in the 16-bit
                 // type the exact version runs and no conversion stream is drawn.
+                // A mass-action propensity is zero when a count is below its
+                // order; with every count at or above its species' largest
+                // order no guard can apply, and the version without them runs.
+                // Each version computes the same values where it runs.
                 T a[M];
                 if constexpr (P::SR && !P::SELECTIVE && Md::NCONV > 0) {
                     // counts are never negative; as unsigned, a negative one would
                     // only send the wave to the version that handles every count
-                    u32 mx = (u32)x[0];
-#pragma unroll
-                    for (int s = 1; s < N; ++s)
-                        mx = (u32)x[s] > mx ? (u32)x[s] : mx;
-                    if (__builtin_expect((act & lanes(mx > (u32)P::EXACT_INT)) == 0, 1)) {
-                        Md::template propensities<P, true>(x, c, hill, a, pool, NoConv());
+                    if (__builtin_expect(
+                            (act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX))) == 0, 1)) {
+                        Md::template propensities<P, true, false>(x, c, hill, a, pool, NoConv());
                     } else {
-                        // the empty asm keeps this a branch: merged with the exact
-                        // version, the conversion stream would be drawn every event
-                        __asm__ volatile("");
-                        const ConvPool<Md::NCONV, P::SR_B> cpool =
-                            make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
-                        Md::template propensities<P, false>(x, c, hill, a, pool, cpool);
+                        u32 mx = (u32)x[0];
+#pragma unroll
+                        for (int s = 1; s < N; ++s)
+                            mx = (u32)x[s] > mx ? (u32)x[s] : mx;
+                        if ((act & lanes(mx > (u32)P::EXACT_INT)) == 0) {
+                            Md::template propensities<P, true, true>(x, c, hill, a, pool, NoConv());
+                        } else {
+                            // the empty asm keeps this a branch: merged with the exact
+                            // version, the conversion stream would be drawn every event
+                            __asm__ volatile("");
+                            const ConvPool<Md::NCONV, P::SR_B> cpool =
+                                make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
+                            Md::template propensities<P, false, true>(x, c, hill, a, pool, cpool);
+                        }
                     }
+                } else if constexpr (Md::LO_MAX > 0) {
+                    if (__builtin_expect((act & lanes(Md::below(x))) == 0, 1))
+                        Md::template propensities<P, false, false>(x, c, hill, a, pool, NoConv());
+                    else
+                        Md::template propensities<P, false, true>(x, c, hill, a, pool, NoConv());
                 } else {
-                    Md::template propensities<P, false>(x, c, hill, a, pool, NoConv());
+                    Md::template propensities<P, false, false>(x, c, hill, a, pool, NoConv());
                 }
                 if constexpr (F::RING)
                     feed.read(nxt);

@@ -86,7 +86,9 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths):
     log["consumer_done"] = True
 
 
-def producer(sh, D, batch, rng, log, skip=True):
+def producer(sh, D, batch, rng, log, skip=True, start=1):
+    """start: free slots before a batch begins (in the kernel another lane's
+    free slots may start it, so start = 1 covers every lane's case)."""
     e, p, uid = 0, 0, 0
     while not log.get("consumer_done"):
         re = sh.req_e
@@ -107,7 +109,7 @@ def producer(sh, D, batch, rng, log, skip=True):
         else:   # the unsigned distance without the skip: behind reads as a full ring
             ahead = (((p << 8) - (dw & ~0xFF)) & M32) >> 8
         room = D - ahead if (mine and ahead < D) else 0
-        if room == 0:
+        if room < start:
             yield                                             # sleep
             continue
         k = min(room, batch)
@@ -125,7 +127,7 @@ def mixed_lengths(r):
 
 
 def run(seed, D=16, batch=8, p_producer=0.5, n_traj=300, start=None, skip=True, lengths=mixed_lengths,
-        hold_after_claim=0):
+        hold_after_claim=0, batch_start=1):
     """hold_after_claim: the producer does not run for that many steps after each
     claim (it sees the claim late, after the lane has formed draws itself)."""
     rng = random.Random(seed)
@@ -133,7 +135,7 @@ def run(seed, D=16, batch=8, p_producer=0.5, n_traj=300, start=None, skip=True, 
     log = {"hits": 0, "misses": 0, "made": 0, "step": 0, "claim_step": 0}
     start = start or (lambda r: r.randint(0, 50))
     c = consumer(sh, D, rng, n_traj, start, log, lengths)
-    pr = producer(sh, D, batch, rng, log, skip)
+    pr = producer(sh, D, batch, rng, log, skip, batch_start)
     live = {"c": c, "p": pr}
     while "c" in live:
         held = log["step"] - log["claim_step"] < hold_after_claim
@@ -209,10 +211,12 @@ def test_event_index_crosses_the_24_bit_wrap(seed):
     assert log["hits"] > 0
 
 
-@pytest.mark.parametrize("D,batch", [(2, 2), (4, 4), (8, 4), (16, 8)])
-def test_ring_depths_and_batches(D, batch):
+@pytest.mark.parametrize("D,batch,batch_start", [(2, 2, 1), (4, 4, 1), (8, 4, 1), (16, 8, 1), (16, 6, 6),
+                                                 (16, 8, 4), (8, 4, 4), (2, 1, 1)])
+def test_ring_depths_and_batches(D, batch, batch_start):
     for seed in range(3):
-        run(300 + seed, D=D, batch=batch)
+        log = run(300 + seed, D=D, batch=batch, batch_start=batch_start)
+        assert log["hits"] > 0
 
 
 def test_a_late_producer_skips_ahead_and_keeps_up():
