@@ -125,6 +125,33 @@ def test_count_conversion_across_exact_integer_limit(gpu, orc, mode, levels):
              wl.snapshot_grid(1.5, 7), mode, seed=11, set_rate=rates, traj_per_set=70, max_events=200_000)
 
 
+def low_count_network():
+    """Two species whose counts sit near the reactant orders (means about 8
+    and 12): X + Y -> X and 2X -> X, 3Y -> 2Y. Lanes dip below the orders now
+    and then, so a wave moves between the propensity version without zero
+    guards (every count at or above its largest order: 2 for X, 3 for Y) and
+    the guarded one, and the start (0, 0) is guarded."""
+    return wl._build("low_count", ["X", "Y"], [
+        {"change": {"X": +1}, "k": 8.0},
+        {"reactants": {"X": 1}, "change": {"X": -1}, "k": 1.0},
+        {"change": {"Y": +1}, "k": 12.0},
+        {"reactants": {"Y": 1}, "change": {"Y": -1}, "k": 1.0},
+        {"reactants": {"X": 1, "Y": 1}, "change": {"Y": -1}, "k": 0.02},
+        {"reactants": {"X": 2}, "change": {"X": -1}, "k": 0.05},
+        {"reactants": {"Y": 3}, "change": {"Y": -1}, "k": 0.01},
+    ])
+
+
+@pytest.mark.parametrize("mode,launch", [("FP64", {}), ("FP32", {}), ("MIX_F16_SR", {}), ("MIX_F16_RTN", {}),
+                                         ("UNI_F16_SR", {}), ("UNI_BF16_SR_NORM", {}),
+                                         ("MIX_F16_SR", {"block_size": 512}), ("FP64", {"block_size": 512})])
+def test_zero_guards_at_low_counts(gpu, orc, mode, launch):
+    # counts crossing the reactant orders: the guard-free and guarded
+    # propensity versions must agree with the oracle's guarded definition
+    run_both(gpu, orc, low_count_network(), np.array([0, 0], np.int32), 64 * 40, 20.0,
+             wl.snapshot_grid(20.0, 21), mode, seed=5, **launch)
+
+
 def run_records(gpu, orc, spec, x0, n, t_end, snap_t, mode, mask, cap, *, seed=1, **launch):
     m = gpu.Model(spec)
     item = {"model": m, "x0": x0, "n_traj": n, "record": (mask, cap)}
