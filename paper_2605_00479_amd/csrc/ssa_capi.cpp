@@ -207,7 +207,7 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
             for (int s = 0; s < md.N; ++s) {
                 int os = md.order[(size_t)j * md.N + s];
                 for (int i = 0; i < os; ++i) {
-                    o << "      acc = P::mul(acc, P::template cvt<EXACT>(x[" << s << "] - " << i << ", cpool.hw("
+                    o << "      acc = P::mul(acc, P::template cvt_sub<EXACT>(x[" << s << "], " << i << ", cpool.hw("
                       << cslot << ")), pool.hw(" << slot << "));\n";
                     slot += 1;
                     cslot += 1;

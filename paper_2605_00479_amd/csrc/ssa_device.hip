@@ -218,6 +218,9 @@ struct PrecF64 {
     static constexpr int SR_B = 16;
     template <bool EXACT>
     __device__ static T cvt(i32 v, u32) { return (double)v; }
+    // (x - i) converted: x converted once, then an exact binary64 subtraction
+    template <bool EXACT>
+    __device__ static T cvt_sub(i32 x, i32 i, u32) { return (double)x - (double)i; }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
     __device__ static T add(T a, T b, u32) { return a + b; }
@@ -236,6 +239,8 @@ struct PrecF32 {
     static constexpr int SR_B = 16;
     template <bool EXACT>
     __device__ static T cvt(i32 v, u32) { return (float)v; }
+    template <bool EXACT>
+    __device__ static T cvt_sub(i32 x, i32 i, u32 rb) { return cvt<EXACT>(x - i, rb); }
     __device__ static T mul(T a, T b, u32) { return a * b; }
     __device__ static T div(T a, T b, u32) { return a / b; }
     __device__ static T add(T a, T b, u32) { return a + b; }
@@ -309,6 +314,16 @@ struct Prec16 {
             return (float)v;
         else
             return rnd16<FMT, SR_OPS>((float)v, rb);
+    }
+    // (x - i) converted. With |x| within the exact-integer limit the binary32
+    // subtraction of the converted x is exact, and x is converted once.
+    template <bool EXACT>
+    __device__ static T cvt_sub(i32 x, i32 i, u32 rb)
+    {
+        if constexpr (EXACT)
+            return (float)x - (float)i;
+        else
+            return rnd16<FMT, SR_OPS>((float)(x - i), rb);
     }
     __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(mul32<FMT>(a, b), rb); }
     __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a / b, rb); }
