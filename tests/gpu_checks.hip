@@ -6,8 +6,8 @@
 //    (B = 13 for fp16: bits 31..19; B = 16 for bf16: bits 31..16), so a
 //    B-bit random field shifted to the top may carry the neighbouring
 //    fields below it.
-//  * div_rn_inrange (the short fma division) returns the IEEE quotient for
-//    every log argument and for -ln(u1) / a0 over the fp16 ranges.
+//  * the short fma divisions return the IEEE quotient: div_rn_log for every
+//    log argument, div_rn_inrange for -ln(u1) / a0 over the fp16 ranges.
 //
 // Test infrastructure: built next to the tests, loaded by them only.
 #include <hip/hip_runtime.h>
@@ -51,7 +51,7 @@ __global__ void check_div_log(unsigned long long *cnt)
     for (uint32_t b = lo + blockIdx.x * blockDim.x + threadIdx.x; b < hi; b += gridDim.x * blockDim.x) {
         const float f = __uint_as_float(b);
         const float num = f - 1.0f, den = f + 1.0f;
-        if (__float_as_uint(div_rn_inrange(num, den)) != __float_as_uint(num / den))
+        if (__float_as_uint(div_rn_log(num, den)) != __float_as_uint(num / den))
             atomicAdd(&cnt[0], 1ull);
     }
 }
@@ -106,8 +106,8 @@ int gpu_check_sr_lowbits(unsigned long long n, unsigned long long *out)
     return finish(d, out, 2);
 }
 
-// Mismatches of div_rn_inrange against the IEEE division: out[0] over every
-// log argument, out[1] over the -ln(u1) / a0 sweep (see check_div_tau).
+// Mismatches against the IEEE division: out[0] div_rn_log over every log
+// argument, out[1] div_rn_inrange over the -ln(u1) / a0 sweep (see check_div_tau).
 int gpu_check_division(unsigned int step, int n_den, unsigned long long *out)
 {
     if (step == 0 || n_den < 1)

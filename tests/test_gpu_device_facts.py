@@ -6,9 +6,9 @@ device template):
   (13 for fp16, 16 for bf16), so the kernel may hand a conversion a packed
   word whose low bits belong to other random fields (the rounding rule the
   oracle states, on the field alone, is then unchanged);
-* the short fma division (div_rn_inrange) returns the IEEE quotient on every
-  log argument and on -ln(u1)/a0 over the fp16 ranges, so the kernel's
-  waiting times equal the oracle's correctly rounded divisions.
+* the short fma divisions return the IEEE quotient: div_rn_log on every log
+  argument, div_rn_inrange on -ln(u1)/a0 over the fp16 ranges, so the kernel's
+  logarithms and waiting times equal the oracle's correctly rounded divisions.
 """
 import ctypes
 import os
