@@ -255,8 +255,10 @@ typedef struct ssa_tune_result {
 /* Launch-shape autotuner. Runs desc's workload (into scratch outputs owned by
  * the library; desc's output pointers are ignored) once per candidate shape:
  * block size 64 or 256; grid holding 1, 2 or 4 waves per SIMD with lane
- * refill, or one lane per trajectory; one launch, 4 even snapshot windows, or
- * a first window of a tenth of the rows followed by 1 or 2 windows. Times
+ * refill, or one lane per trajectory, and 512 (producer waves) with one
+ * workgroup per CU; one launch, 4 even snapshot windows, a first window of a
+ * tenth of the rows followed by 1 or 2 windows, or of 15% or 20% of the rows
+ * followed by 1. Times
  * each with HIP events, keeps the fastest in memory and in
  * <cache dir>/tune.txt, keyed by the generated kernel and the workload shape
  * (ensemble sizes, snapshot count, t_end, max_events). Later runs of the same

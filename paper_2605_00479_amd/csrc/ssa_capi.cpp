@@ -1450,7 +1450,8 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
     std::vector<Cand> cands;
     // one launch; 4 even windows; a first window of about a tenth of the rows
     // (it measures every trajectory's event rate, so the longest start first)
-    // followed by one or two windows
+    // followed by one or two windows, or of about 15% or 20% of the rows
+    // followed by one (a longer first look sorts later state switches in too)
     struct ChunkOpt {
         int chunks, window;
     };
@@ -1461,6 +1462,11 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         const int w = std::max(1, desc->n_snap / 10);
         chunk_opts.push_back({2, w});
         chunk_opts.push_back({3, w});
+        for (int pct : {15, 20}) {
+            const int wl = std::max(1, desc->n_snap * pct / 100);
+            if (wl != w && wl <= desc->n_snap - 1)
+                chunk_opts.push_back({2, wl});
+        }
     }
     for (int block : {64, 256}) {
         int per_cu = 0;
