@@ -261,8 +261,9 @@ def main():
         "speedup_vs_fp64": value / ref_value,
         "fidelity": fidelity,
         "status_counts": main_res["status_counts"],
-        "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
-        "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches")},
+        "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches", "first_window")},
+        "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches",
+                                                          "first_window")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS,
                      "traffic": measured_traffic(args.mode, ve["file"]),

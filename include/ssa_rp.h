@@ -237,6 +237,7 @@ typedef struct ssa_run_info {
     int32_t grid_size;
     int32_t vgprs;            /* not known: -1 */
     uint64_t total_events;    /* sum of events over all trajectories */
+    int32_t first_window;     /* snapshot rows of the first launch (0: even windows) */
 } ssa_run_info;
 
 /* Fill info for a run (waits for it). */

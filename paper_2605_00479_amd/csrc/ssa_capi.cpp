@@ -1418,6 +1418,7 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
             tot += v;
     }
     info->total_events = tot;
+    info->first_window = run->n_launch > 1 ? run->first_window : 0;
     return SSA_OK;
 }
 

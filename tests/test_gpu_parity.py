@@ -304,12 +304,14 @@ def test_full_size_schlogl_sampled(gpu, orc):
     ids spread over the whole range, in the default launch and in the
     benchmark's launch shapes: one event-loop wave per SIMD forming its own
     draws (1024 waves of 64) or paired with a draw-producing wave (256
-    workgroups of 512), two snapshot windows with a first window of 10 rows."""
+    workgroups of 512), two snapshot windows with a first window of 10 or 15
+    rows (the autotuner's choices for the two modes)."""
     W = wl.config_schlogl()
     it = W.items[0]
     sample = np.unique(np.concatenate([np.arange(0, 100_000, 997), [99_999, 65_535, 65_536]]))
     launches = ({}, dict(block_size=64, grid_size=1024, n_chunks=2, first_window=10),
-                dict(block_size=512, grid_size=256, n_chunks=2, first_window=10))
+                dict(block_size=512, grid_size=256, n_chunks=2, first_window=10),
+                dict(block_size=512, grid_size=256, n_chunks=2, first_window=15))
     for mode in ("FP64", "MIX_F16_SR"):
         for launch in launches:
             run, snap, st = run_both(gpu, orc, it.model, it.x0, it.n_traj, W.t_end, W.snap_t, mode, seed=W.seed,
