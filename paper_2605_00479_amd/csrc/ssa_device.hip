@@ -104,6 +104,23 @@ __device__ __forceinline__ float div_rn_log(float a, float b)
     return __builtin_fmaf(rem, r, q);
 }
 
+// (f - 1) / (f + 1) for binary64 f in [1/2, 2): the compiler's IEEE division
+// without its operand scaling and special-case fix-up, which leave these
+// operands unchanged (the numerator is 0 or at least 2^-53 in magnitude, the
+// denominator in [1.5, 3), the quotient normal): reciprocal, two Newton steps,
+// product, and the remainder correction as a plain fma.
+__device__ __forceinline__ double div_rn_log64(double a, double b)
+{
+    const double r0 = __builtin_amdgcn_rcp(b);
+    const double e0 = __builtin_fma(-b, r0, 1.0);
+    const double r1 = __builtin_fma(r0, e0, r0);
+    const double e1 = __builtin_fma(-b, r1, 1.0);
+    const double r2 = __builtin_fma(r1, e1, r1);
+    const double q = a * r2;
+    const double rem = __builtin_fma(-b, q, a);
+    return __builtin_fma(rem, r2, q);
+}
+
 __device__ __forceinline__ float div_rn_inrange(float a, float b)
 {
     float r = __builtin_amdgcn_rcpf(b);
@@ -133,7 +150,7 @@ __device__ __forceinline__ double neg_log64(double u)
         f = f * 0.5;
         e = e + 1;
     }
-    double s = (f - 1.0) / (f + 1.0);
+    double s = div_rn_log64(f - 1.0, f + 1.0);
     double z = s * s;
     double p = 0x1.8618618618618p-5;         // 1/21
     p = __builtin_fma(p, z, 0x1.af286bca1af28p-5); // 1/19

@@ -7,7 +7,8 @@
 //    B-bit random field shifted to the top may carry the neighbouring
 //    fields below it.
 //  * the short fma divisions return the IEEE quotient: div_rn_log for every
-//    log argument, div_rn_inrange for -ln(u1) / a0 over the fp16 ranges.
+//    log argument, div_rn_inrange for -ln(u1) / a0 over the fp16 ranges,
+//    div_rn_log64 for binary64 log arguments (a hashed sample and the edges).
 //
 // Test infrastructure: built next to the tests, loaded by them only.
 #include <hip/hip_runtime.h>
@@ -74,6 +75,29 @@ __global__ void check_div_tau(uint32_t step, int n_den, unsigned long long *cnt)
     }
 }
 
+// binary64 f in [1/2, 2): n hashed mantissas per exponent (f in [1/2, 1) and
+// [1, 2)), plus the 64 mantissas at each end of both binades
+__global__ void check_div_log64(unsigned long long n, unsigned long long *cnt)
+{
+    const unsigned long long total = 2 * (n + 128);
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < total;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long j = i >> 1;
+        const uint64_t ex = (i & 1) ? 0x3FE0000000000000ull : 0x3FF0000000000000ull;
+        uint64_t m;
+        if (j < 64)
+            m = j;
+        else if (j < 128)
+            m = 0x000FFFFFFFFFFFFFull - (j - 64);
+        else
+            m = (((uint64_t)mix64(j) << 32) | mix64(j ^ 0x9E3779B97F4A7C15ull)) & 0x000FFFFFFFFFFFFFull;
+        const double f = __longlong_as_double((long long)(ex | m));
+        const double num = f - 1.0, den = f + 1.0;
+        if (__double_as_longlong(div_rn_log64(num, den)) != __double_as_longlong(num / den))
+            atomicAdd(&cnt[0], 1ull);
+    }
+}
+
 int finish(unsigned long long *d, unsigned long long *h, int n)
 {
     if (hipDeviceSynchronize() != hipSuccess)
@@ -119,6 +143,18 @@ int gpu_check_division(unsigned int step, int n_den, unsigned long long *out)
     check_div_log<<<4096, 256>>>(d);
     check_div_tau<<<4096, 256>>>(step, n_den, d + 1);
     return finish(d, out, 2);
+}
+
+// Mismatches of div_rn_log64 against the IEEE binary64 division over
+// 2 (n + 128) log arguments (see check_div_log64): out[0].
+int gpu_check_division64(unsigned long long n, unsigned long long *out)
+{
+    unsigned long long *d = nullptr;
+    int rc = alloc_counters(&d, 1);
+    if (rc)
+        return rc;
+    check_div_log64<<<4096, 256>>>(n, d);
+    return finish(d, out, 1);
 }
 
 }  // extern "C"
