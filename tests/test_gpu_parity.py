@@ -152,6 +152,39 @@ def test_zero_guards_at_low_counts(gpu, orc, mode, launch):
              wl.snapshot_grid(20.0, 21), mode, seed=5, **launch)
 
 
+def largest_network():
+    """32 species and 64 reactions (the C ABI's limits): per species a birth
+    (every eighth one repressed by its neighbour through a Hill law) and a
+    loss, the losses alternating between first order, a bimolecular reaction
+    with the next species and a dimerisation. In the 16-bit modes its rounding
+    fields outgrow the producer waves' LDS rings: mixed fp16 SR gets rings of
+    depth 2, uniform fp16 SR none (the 512-thread kernel then runs eight
+    event-loop waves that form their own draws)."""
+    sp = [f"X{i}" for i in range(32)]
+    rx = []
+    for i in range(32):
+        if i % 8 == 7:
+            rx.append({"change": {sp[i]: +1}, "hill": ("repress", sp[i - 1], 0.5, 6.0, 4.0, 2)})
+        else:
+            rx.append({"change": {sp[i]: +1}, "k": 4.0 + (i % 3)})
+        if i % 3 == 0:
+            rx.append({"reactants": {sp[i]: 1}, "change": {sp[i]: -1}, "k": 0.6})
+        elif i % 3 == 1:
+            rx.append({"reactants": {sp[i]: 1, sp[(i + 1) % 32]: 1}, "change": {sp[i]: -1}, "k": 0.08})
+        else:
+            rx.append({"reactants": {sp[i]: 2}, "change": {sp[i]: -1}, "k": 0.05})
+    return wl._build("largest", sp, rx)
+
+
+@pytest.mark.parametrize("mode,launch", [("FP64", {}), ("MIX_F16_SR", {}), ("UNI_F16_SR", {}),
+                                         ("FP64", {"block_size": 512}), ("MIX_F16_SR", {"block_size": 512}),
+                                         ("UNI_F16_SR", {"block_size": 512})])
+def test_largest_network(gpu, orc, mode, launch):
+    m = largest_network()
+    assert m.n_species == 32 and m.n_reactions == 64
+    run_both(gpu, orc, m, np.full(32, 3, np.int32), 64 * 12, 2.0, wl.snapshot_grid(2.0, 5), mode, seed=9, **launch)
+
+
 def run_records(gpu, orc, spec, x0, n, t_end, snap_t, mode, mask, cap, *, seed=1, **launch):
     m = gpu.Model(spec)
     item = {"model": m, "x0": x0, "n_traj": n, "record": (mask, cap)}
