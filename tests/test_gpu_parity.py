@@ -352,6 +352,70 @@ def test_full_size_schlogl_sampled(gpu, orc):
             assert np.all(run.stats(0)["status"] == 0)
 
 
+def sampled_parity(gpu, orc, W, mode, samples, **launch):
+    """Run workload W whole on the GPU and compare the trajectory ids in
+    samples[i] (local to item i) with the oracle. Snapshot rows are gathered
+    on the device, so the multi-gigabyte outputs never cross to the host."""
+    import torch
+    items = gpu.items_from_workload(W)
+    print(f"[gpu-parity] full-size {W.name} mode={mode} n={W.n_traj} launch={launch}", flush=True)
+    run = gpu.ssa_ensemble_run(items, W.t_end, W.snap_t, W.seed, mode, max_events=W.max_events, **launch)
+    run.wait()
+    base = 0
+    for i, it in enumerate(W.items):
+        idx = np.asarray(samples[i], dtype=np.int64)
+        snap = run.tensors(i)[0][:, :, torch.from_numpy(idx).cuda()].cpu().numpy()
+        st = {k: v[idx] for k, v in run.stats(i).items()}
+        ref = orc.simulate(it.model, mode, it.x0, W.t_end, W.snap_t, W.seed, indices=idx, traj_id_base=base,
+                           max_events=W.max_events, set_rate=it.set_rate, traj_per_set=it.traj_per_set,
+                           threads=ORACLE_THREADS)
+        assert_parity(ref, snap, st, mode, f"{W.name}/{it.model.name}")
+        base += it.n_traj
+    info = run.info()
+    run.destroy()
+    del run
+    torch.cuda.empty_cache()
+    return info
+
+
+def spread(n, count, extra=()):
+    """About `count` ids spread over range(n), plus its ends and `extra`."""
+    ids = np.arange(0, n, max(1, n // count))
+    return np.unique(np.concatenate([ids, [0, n - 1], np.asarray(extra, dtype=np.int64)]).astype(np.int64))
+
+
+@pytest.mark.parametrize("mode", ["FP64", "UNI_F16_SR_NORM", "UNI_BF16_SR"])
+def test_full_size_telegraph_sampled(gpu, orc, mode):
+    """Telegraph, 1,000,000 trajectories to T_end = 200 with 201 snapshot
+    rows (2.4 GB of snapshots), in the default launch."""
+    W = wl.config_telegraph()
+    sampled_parity(gpu, orc, W, mode, [spread(W.n_traj, 120, [65_535, 65_536, 524_287])])
+
+
+@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR"])
+def test_full_size_dimer_sweep_sampled(gpu, orc, mode):
+    """Open dimer, 4,096 parameter sets x 256 trajectories in one launch,
+    lengths spread over three decades: ids spread over the sets plus both ends
+    of the sets with the largest and smallest production rate."""
+    W = wl.config_dimer_sweep()
+    it = W.items[0]
+    hi, lo = int(np.argmax(it.set_rate[:, 0])), int(np.argmin(it.set_rate[:, 0]))
+    tps = it.traj_per_set
+    extra = [hi * tps, hi * tps + tps - 1, lo * tps, lo * tps + tps - 1]
+    sampled_parity(gpu, orc, W, mode, [spread(W.n_traj, 100, extra)])
+
+
+@pytest.mark.parametrize("mode,launch", [("FP64", {}), ("MIX_F16_SR", dict(block_size=512, grid_size=256)),
+                                         ("MIX_BF16_SR", dict(block_size=512, grid_size=256))])
+def test_full_size_heterogeneous_sampled(gpu, orc, mode, launch):
+    """All five networks in one launch, 800,000 trajectories each, to
+    T_end = 500 with 501 snapshot rows (20.8 GB of snapshots; item ids and
+    snapshot offsets beyond 2^31 elements): 16 ids per network."""
+    W = wl.config_heterogeneous()
+    info = sampled_parity(gpu, orc, W, mode, [spread(it.n_traj, 14) for it in W.items], **launch)
+    assert info["total_events"] > 10 ** 12
+
+
 # ---------------------------------------------------------------------------
 # Producer waves (block_size 512): waves 0-3 of a workgroup run trajectories,
 # wave w + 4 forms wave w's draws ahead through an LDS ring. Same results as
