@@ -233,8 +233,8 @@ def main():
     def per_event(mode, res):
         f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode)
         c = {**valu_count.count(f), "file": f}
-        if len(items) > 1:
-            ev = np.asarray(res["item_events"])
+        ev = np.asarray(res["item_events"])
+        if len(items) > 1 and ev.sum() > 0:
             per = [valu_count.count(ssa.ssa_kernel_file([it], W.t_end, W.snap_t, mode)) for it in items]
             for key in ("valu_slots", "valu_insts"):
                 c[key] = float(sum(e * p[key] for e, p in zip(ev, per)) / ev.sum())
