@@ -18,9 +18,12 @@
  *   - Stochastic rounding, SR(x) = x- w.p. (x+ - x)/(x+ - x-), else x+:
  *     Sec. 3.3 (the SR equation); applied at every arithmetic op (Sec. 3.3).
  *   - fp16/bf16 format parameters: Table "tab:formats" (Sec. 3.1).
- *   - Propensity normalisation: named in the abstract only; the reading used
- *     here (divide by the running maximum propensity) is the one recorded in
- *     the design notes.
+ *   - Propensity normalisation: named in the abstract only; read here as
+ *     dividing every propensity by the running maximum of the largest
+ *     propensity over the steps so far (current step included).
+ * Pins: the tests hold each part to closed forms, exhaustive checks or
+ * brute force. The repressilator as a whole has none (parity unpinned); its
+ * Hill and first-order laws are pinned separately.
  * The paper does not fix the random number generator, the uniform interval,
  * the op order inside a propensity, or how SR bits are drawn. The readings
  * implemented here are:
