@@ -413,3 +413,37 @@ def test_selective_sr_draws_only_for_sums_and_clock(orc):
     b = run(orc, m, "UNI_F16_SRA", [0], 5.0, [5.0], 500, seed=20, threads=1)
     for k in a:
         np.testing.assert_array_equal(a[k], b[k])
+
+
+# --------------------------------------------------------------------------- propensity normalisation
+@pytest.mark.parametrize("mode,bd_tol", [("UNI_F16_SR_NORM", None), ("UNI_BF16_SR_NORM", 0.5)])
+def test_normalised_uniform_modes_keep_the_laws(orc, mode, bd_tol):
+    """Running-max normalisation (abstract; divide every propensity by m, the
+    largest propensity seen so far, and the waiting time by m again) leaves
+    the law of the process unchanged, so with stochastic rounding the
+    normalised uniform modes stay on the exact laws:
+
+    * birth-death kb = 20, kd = 1 from 0: X(30) ~ Poisson(20(1 - e^-30)).
+      fp16: mean within 4 standard errors. bf16 uniform SR carries a small
+      known bias on this network (the paper's uniform BF16+SR row of Table
+      tab:birth-death fails KS), so its mean is held to 20 +- 0.5;
+    * telegraph k_on = 0.05, k_off = 0.1, k_m = 20, beta = 1 at T = 200
+      (relaxed): stationary mean k_m k_on / (beta (k_on + k_off)) = 20/3 within
+      4 standard errors, Fano factor 1 + k_m k_off / ((k_on + k_off)(k_on +
+      k_off + beta)) within 8%.
+
+    A waiting time not divided by m stretches time m-fold (birth-death mean
+    about 15.5, telegraph about 11.6); summands not divided by m shrink it
+    m-fold (telegraph mean about 2.7, not relaxed by T)."""
+    bd = run(orc, wl.birth_death(20.0, 1.0), mode, [0], 30.0, [30.0], 20_000, seed=17,
+             max_events=100_000)["snap"][0, 0]
+    lam = 20.0 * (1 - math.exp(-30.0))
+    tol = bd_tol if bd_tol is not None else 4 * math.sqrt(lam / bd.size)
+    assert abs(bd.mean() - lam) < tol, (mode, bd.mean())
+    W = wl.config_telegraph()
+    it = W.items[0]
+    m = run(orc, it.model, mode, it.x0, 200.0, [200.0], 20_000, seed=17, max_events=W.max_events)["snap"][0, 2]
+    mean = 20.0 * 0.05 / 0.15
+    fano = 1 + 20.0 * 0.1 / (0.15 * 1.15)
+    assert abs(m.mean() - mean) < 4 * math.sqrt(mean * fano / m.size), (mode, m.mean())
+    assert abs(m.var(ddof=1) / m.mean() - fano) < 0.08 * fano, (mode, m.var(ddof=1) / m.mean())

@@ -149,6 +149,19 @@ def transient_snapshots_fail(lib):
     return not np.all(r["snap"][0, 0] == 0)
 
 
+def normalised_laws_fail(lib):
+    """The normalisation pin: uniform fp16 SR with running-max normalisation on
+    the relaxed telegraph (mean 20/3) and birth-death 20/1 at T = 30 (mean 20)."""
+    tel = oracle.simulate(wl.telegraph(), "UNI_F16_SR_NORM", [1, 0, 0], 200.0, [200.0], 17, n_traj=1000,
+                          max_events=2584 * 64, threads=8, lib=lib)["snap"][0, 2]
+    mean, fano = 20.0 / 3.0, 1 + 20.0 * 0.1 / (0.15 * 1.15)
+    if abs(tel.mean() - mean) > 4 * math.sqrt(mean * fano / tel.size):
+        return True
+    bd = oracle.simulate(wl.birth_death(20.0, 1.0), "UNI_F16_SR_NORM", [0], 30.0, [30.0], 17, n_traj=5000,
+                         max_events=100000, threads=8, lib=lib)["snap"][0, 0]
+    return abs(bd.mean() - 20.0) > 4 * math.sqrt(20.0 / bd.size)
+
+
 MUTATIONS = [
     ("philox key not advanced", "            k0 += PHILOX_WEYL0;\n            k1 += PHILOX_WEYL1;\n", "", kat_fails),
     ("philox low halves swapped", "        uint32_t n1 = lo1;", "        uint32_t n1 = lo0;", kat_fails),
@@ -179,6 +192,10 @@ MUTATIONS = [
      "            S[j] = rnd(&RA, S[j - 1] + a[j], slot_sum + j - 1);", mixed_equals_fp32_fails),
     ("uniform clock kept in binary32", "            t_new = rnd(&RA, t + tau, slot_time);", "            t_new = t + tau;",
      uniform_stagnation_fails),
+    ("waiting time not divided by the running max", "                tau = rnd(&R, tau / m, slot_taum);\n", "",
+     normalised_laws_fail),
+    ("summands not divided by the running max", "                a[j] = rnd(&R, a[j] / m, slot_norm + j);",
+     "                a[j] = rnd(&R, a[j], slot_norm + j);", normalised_laws_fail),
 ]
 
 
@@ -193,7 +210,8 @@ def test_pin_detects_planted_mistake(tmp_path, name, find, repl, detect):
 
 @pytest.mark.parametrize("detect", [kat_fails, uniform_range_fails, rne_fails, sr_probability_fails,
                                     birth_death_law_fails, closed_dimer_law_fails, hill_law_fails,
-                                    mixed_equals_fp32_fails, uniform_stagnation_fails, transient_snapshots_fail])
+                                    mixed_equals_fp32_fails, uniform_stagnation_fails, transient_snapshots_fail,
+                                    normalised_laws_fail])
 def test_detectors_accept_the_unaltered_oracle(tmp_path, detect):
     path = oracle.build_variant(open(SRC).read(), str(tmp_path / "same.so"))
     assert not detect(oracle._open(path))
@@ -202,3 +220,11 @@ def test_detectors_accept_the_unaltered_oracle(tmp_path, detect):
 # Not detectable by a pin: the tie rules (S_j > target vs >=, snapshot t_k < t_new vs <=)
 # differ only when two binary64 values coincide exactly, probability about 2^-53 per
 # event; the GPU parity tests compare them with the kernel over ~10^9 events instead.
+#
+# Normalisation by the current step's largest propensity instead of the running
+# maximum is not detectable either: binary floating point is scale invariant, so
+# dividing every summand and the waiting time by another positive m changes only
+# where values fall relative to the subnormal and overflow ranges, and with
+# counts and rates of ordinary size the result is the same law (checked: the
+# birth-death and telegraph means of such an oracle agree with the pinned one to
+# within their standard errors). The kernel's parity test fixes the running max.
