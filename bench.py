@@ -1,13 +1,17 @@
 """Benchmark: SSA events/s on one MI355X, mixed FP16 with stochastic rounding
-(the reported value) against the FP64 direct method, on the Schloegl ensemble
-(100,000 trajectories, T_end = 10, 101 snapshots) unless --config names
-another configured workload.
+(the reported value) against the FP64 direct method, on the open-dimerisation
+parameter sweep in one persistent launch (4,096 log-uniform parameter sets x
+256 trajectories, T_end = 50, 51 snapshots) unless --config names another
+configured workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config schlogl]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config dimer_sweep]
 
 A step is one complete ensemble run (every trajectory from t = 0 to T_end:
 RNG draws, propensities, sums, waiting times, snapshot stores, selection and
-integer updates) through the C ABI. Prints one JSON line.
+integer updates) through the C ABI. Prints one JSON line. `value` counts only
+when the reduced-precision end-time marginals pass KS (p > 0.05, independent
+seeds) against the FP64 ensemble; otherwise it is null and the measured rate
+is reported as `value_failing_fidelity`.
 """
 from __future__ import annotations
 
@@ -34,7 +38,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--config", default="schlogl")
+    p.add_argument("--config", default="dimer_sweep")
     p.add_argument("--n-traj", type=int, default=0, help="override the ensemble size (0: the config's)")
     p.add_argument("--mode", default="MIX_F16_SR")
     p.add_argument("--ref-mode", default="FP64")
@@ -69,11 +73,14 @@ def launch(ssa, items, W, mode, seed, args):
 
 
 def marginals(run, W):
+    """End-time rows of the marginal species, taken from the run's device
+    output tensors (only these rows cross to the host)."""
     out = {}
     for i, it in enumerate(W.items):
-        snap = run.snapshots(i)
+        snap = run.tensors(i)[0]
         for s in MARGINALS.get(it.model.name, (0,)):
-            out[f"{it.model.name}:{it.model.species[s]}"] = snap[-1, s].copy() if snap.shape[0] else np.zeros(0)
+            out[f"{it.model.name}:{it.model.species[s]}"] = (snap[-1, s].cpu().numpy().copy() if snap.shape[0]
+                                                            else np.zeros(0))
     return out
 
 
@@ -154,16 +161,20 @@ def copy_calib(log, nbytes=1 << 30):
     return {"bytes": nbytes, "ms": ms.value, "GB_per_s_read_plus_write": gbs}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ssa_kernel_schlogl_100k_traffic.md")
+TRAFFIC_FILES = {"schlogl": "ssa_kernel_schlogl_100k_traffic.md",
+                 "dimer_sweep": "ssa_kernel_dimer_sweep_traffic.md"}
 
 
-def measured_traffic(mode, kernel_file):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on this exact kernel object (rows: | mode | object | ... | bytes |)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(workload, mode, kernel_file):
+    """HBM bytes per step from the committed counter summary of the workload,
+    if it was taken on this exact kernel object (rows: | mode | object | ... |
+    bytes |)."""
+    name = TRAFFIC_FILES.get(workload)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
         return None
     obj = os.path.basename(kernel_file)
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) >= 3 and cells[0] == mode and cells[1] == obj:
             try:
@@ -173,20 +184,46 @@ def measured_traffic(mode, kernel_file):
     return None
 
 
+def physical_cores():
+    """Distinct (package, core) pairs among the CPUs this process may run on."""
+    try:
+        allowed = os.sched_getaffinity(0)
+        pairs, cpu, phys = set(), None, None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    cpu = int(v)
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id" and cpu in allowed:
+                    pairs.add((phys, v))
+        return len(pairs) or None
+    except (OSError, ValueError):
+        return None
+
+
 def cpu_baseline(W, mode, n_sample, log):
+    """The oracle on the host's cores, on every k-th trajectory of the same
+    ensemble (k = E / n_sample, so the sample spans every parameter set)."""
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    allowed = len(os.sched_getaffinity(0))
+    threads = min(16, allowed)
     it = W.items[0]
     n = min(n_sample, it.n_traj)
-    idx = np.arange(n, dtype=np.int64)
+    stride = max(1, it.n_traj // n)
+    idx = np.arange(0, stride * n, stride, dtype=np.int64)
     t0 = time.perf_counter()
     r = oracle.simulate(it.model, mode, it.x0, W.t_end, W.snap_t, W.seed, indices=idx, max_events=W.max_events,
                         set_rate=it.set_rate, traj_per_set=it.traj_per_set, threads=threads)
     dt = time.perf_counter() - t0
     ev = int(r["n_events"].sum())
     log(f"[bench] cpu oracle {mode}: {n} trajectories, {ev} events in {dt:.2f}s on {threads} threads")
-    return {"value": ev / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"trajectories 0..{n - 1} of the same {it.model.name} ensemble, {mode}, full horizon"}
+    return {"value": ev / dt, "unit": "events/s", "cores": threads, "physical_cores": physical_cores(),
+            "cpus_available": allowed, "kind": "oracle",
+            "sample": f"every {stride}th trajectory (ids 0, {stride}, ..., {int(idx[-1])}; {n} in all) of the same "
+                      f"{it.model.name} ensemble, {mode}, full horizon, {ev} events"}
 
 
 def main():
@@ -231,11 +268,12 @@ def main():
     # the work, so each network's slots are counted on its own single-network
     # object and weighted by the events that network fired.
     def per_event(mode, res):
-        f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode)
+        f = ssa.ssa_kernel_file(items, W.t_end, W.snap_t, mode, max_events=W.max_events)
         c = {**valu_count.count(f), "file": f}
         ev = np.asarray(res["item_events"])
         if len(items) > 1 and ev.sum() > 0:
-            per = [valu_count.count(ssa.ssa_kernel_file([it], W.t_end, W.snap_t, mode)) for it in items]
+            per = [valu_count.count(ssa.ssa_kernel_file([it], W.t_end, W.snap_t, mode, max_events=W.max_events))
+                   for it in items]
             for key in ("valu_slots", "valu_insts"):
                 c[key] = float(sum(e * p[key] for e, p in zip(ev, per)) / ev.sum())
         return c
@@ -243,12 +281,16 @@ def main():
     ve, ve_ref = per_event(args.mode, main_res), per_event(args.ref_mode, ref_res)
     ms = main_res["kernel_ms_avg"]
     achieved = main_res["events_per_step"] * ve["valu_slots"] / (ms * 1e-3)
-    value = main_res["events"] / main_res["wall_s"]
+    rate = main_res["events"] / main_res["wall_s"]
+    # the metric counts events/s only where the ensemble passes KS against FP64
+    passed = fidelity is not None and fidelity["ks_pass_all"]
+    value = rate if passed else None
     ref_value = ref_res["events"] / ref_res["wall_s"]
     desc = {"schlogl": "schlogl bistable, X0=250, T_end=10, 101 snapshots",
             "birth_death": "birth-death kb=10 kd=0.1, X0=0, T_end=100, snapshot at 100",
             "telegraph": "telegraph k_on=0.05 k_off=0.1 k_m=20, gene off, T_end=200, 201 snapshots",
-            "dimer_sweep": "open dimer, log-uniform parameter sets (seed 7) x 256, T_end=50, 51 snapshots",
+            "dimer_sweep": "open dimerisation sweep in one launch: 4,096 parameter sets (k1..k4 = 50, 0.1, 0.001, 0.5 "
+                           "each x 10^(2u-1), u from PCG64 seed 7) x 256 trajectories, M0=D0=0, T_end=50, 51 snapshots",
             "heterogeneous": "five networks in one launch, T_end=500, 501 snapshots"}[W.name]
     out_cfg_chunks = main_res["info"]["n_launches"]
     out = {
@@ -272,19 +314,22 @@ def main():
                  "valu_slots_per_event": ve_ref["valu_slots"],
                  "valu_frac": ref_res["events_per_step"] * ve_ref["valu_slots"] / (ref_res["kernel_ms_avg"] * 1e-3)
                  / PEAK_VALU_SLOTS},
-        "speedup_vs_fp64": value / ref_value,
+        "speedup_vs_fp64": rate / ref_value,
         "fidelity": fidelity,
+        "fidelity_gate": "passed" if passed else ("skipped" if fidelity is None else "failed"),
         "status_counts": main_res["status_counts"],
         "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches", "first_window")},
         "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches",
                                                           "first_window")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS,
-                     "traffic": measured_traffic(args.mode, ve["file"]),
+                     "traffic": measured_traffic(W.name, args.mode, ve["file"]),
                      "kernel": "ssa_kernel_pc" if main_res["info"]["block_size"] == 512 else "ssa_kernel",
                      "kernel_object": os.path.basename(ve["file"]), "kernel_ms": ms,
                      "valu_slots_per_event": ve["valu_slots"], "valu_insts_per_event": ve["valu_insts"]},
     }
+    if not passed:
+        out["value_failing_fidelity"] = rate
     out["fp64"]["kernel_object"] = os.path.basename(ve_ref["file"])
     out["fp64"]["kernel"] = "ssa_kernel_pc" if ref_res["info"]["block_size"] == 512 else "ssa_kernel"
     if args.valu_peak:

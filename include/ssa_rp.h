@@ -153,12 +153,19 @@ typedef struct ssa_item {
  *     FP64 and FP32 take accum = MIXED, rounding = RTN, norm = NONE.
  *     norm = RUNNING_MAX and rounding = SR_ACC need a 16-bit format and
  *     accum = UNIFORM.
- *   max_events: per-trajectory event cap (0 = none).
+ *   max_events: per-trajectory event cap; a trajectory that fires it stops
+ *     with SSA_STATUS_CAPPED. 0 = none, allowed for FP64 only: a binary32 or
+ *     16-bit clock stops advancing once the waiting time falls below half its
+ *     spacing (the stagnation of uniform round-to-nearest runs, Sec. 4), and
+ *     such a trajectory would never end (SSA_E_INVALID).
  *   hip_stream: hipStream_t to run on (NULL = the null stream).
  *   n_chunks: 1 runs the horizon in one launch; c > 1 splits the snapshot
- *     rows into c windows, one launch each, replayed from a captured hipGraph;
- *     results are bit-identical to one launch. 0 = the autotuned choice for
- *     this kernel and workload shape if ssa_autotune stored one, else 1.
+ *     rows into c windows, one launch each (with the small kernels that
+ *     reorder claims between them). Up to 16 windows are launched directly on
+ *     hip_stream; a longer sequence is captured once per run into a hipGraph,
+ *     which is launched on hip_stream. Results are bit-identical to one
+ *     launch. 0 = the autotuned choice for this kernel and workload shape if
+ *     ssa_autotune stored one, else 1.
  *   block_size, grid_size: launch shape; 0 = the autotuned choice if stored,
  *     else 256 threads and enough workgroups for one trajectory per lane (up
  *     to what stays resident). block_size a multiple of 64 up to 256, or 512:
@@ -238,6 +245,7 @@ typedef struct ssa_run_info {
     int32_t vgprs;            /* not known: -1 */
     uint64_t total_events;    /* sum of events over all trajectories */
     int32_t first_window;     /* snapshot rows of the first launch (0: even windows) */
+    int32_t graph;            /* 1 if the launches ran as one captured hipGraph */
 } ssa_run_info;
 
 /* Fill info for a run (waits for it). */
@@ -247,7 +255,7 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info);
 typedef struct ssa_tune_result {
     int32_t block_size;   /* threads per workgroup */
     int32_t grid_size;    /* workgroups: sets waves per CU and trajectories per lane */
-    int32_t n_chunks;     /* snapshot windows (hipGraph-replayed launches) */
+    int32_t n_chunks;     /* snapshot windows (one launch each) */
     int32_t first_window; /* snapshot rows of the first window (0: even windows) */
     int32_t n_candidates; /* launch shapes timed */
     double best_ms;       /* device time of the chosen shape */

@@ -5,7 +5,8 @@
 //    generates the network description for the device template
 //    (ssa_device.hip), compiles it with hipRTC for gfx950 (cached in memory
 //    and on disk), uploads tables and launches the persistent kernel, in one
-//    launch or in snapshot-window chunks replayed from a captured hipGraph.
+//    launch or in snapshot-window chunks (direct launches, or beyond
+//    kGraphMinChunks windows one hipGraph captured and launched per run).
 //  * getters copy results out; ssa_run_info_get reports HIP-event timings.
 #include "ssa_rp.h"
 
@@ -695,6 +696,13 @@ int validate_desc(const ssa_run_desc *d)
     int rc = validate_mode(d);
     if (rc != SSA_OK)
         return rc;
+    // A binary32 or 16-bit clock stops advancing once the waiting time falls
+    // below half its spacing at t (round to nearest; Sec. 4 reports the stall
+    // for uniform round-to-nearest runs): such a trajectory fires events
+    // forever, so these clocks need a finite cap.
+    if (d->format != SSA_FMT_FP64 && d->max_events == 0)
+        return fail(SSA_E_INVALID, "max_events must be > 0 unless format is FP64: a binary32 or 16-bit clock "
+                                   "can stop advancing, and the trajectory would then never end");
     if (d->n_chunks < 0 || d->n_chunks > 4096)
         return fail(SSA_E_INVALID, "n_chunks must be in [0, 4096]");
     if (d->block_size != 0 && d->block_size != 512 &&
@@ -800,6 +808,8 @@ struct ssa_run {
     std::vector<ItemBuf> items;
     std::vector<std::pair<void *, size_t>> owned;  // library-owned device buffers (returned to the cache)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool ev1_recorded = false;    // ev1 marks the end of all queued work
+    bool queued = false;          // some work was queued on the streams
     std::vector<hipEvent_t> kev;  // start/stop per launch (non-graph runs)
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;
@@ -1181,6 +1191,7 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
             HIP_TRY(hipEventCreate(&e));
     }
     HIP_TRY(hipEventRecord(r->ev0, r->stream));
+    r->queued = true;
     if (r->graph) {
         HIP_TRY(hipStreamCreateWithFlags(&r->cap, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(r->cap, hipStreamCaptureModeThreadLocal));
@@ -1200,6 +1211,7 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
             return rc;
     }
     HIP_TRY(hipEventRecord(r->ev1, r->stream));
+    r->ev1_recorded = true;
     return SSA_OK;
 }
 
@@ -1207,10 +1219,16 @@ void release(ssa_run *r)
 {
     if (!r)
         return;
-    if (r->ev1)
+    // The buffers go back to the cache only once no queued kernel can still
+    // write them: after ev1, or, where a failure came before ev1 was
+    // recorded, after everything queued on the run's streams.
+    if (r->ev1_recorded) {
         (void)hipEventSynchronize(r->ev1);
-    else
+    } else if (r->queued) {
+        if (r->cap)
+            (void)hipStreamSynchronize(r->cap);
         (void)hipStreamSynchronize(r->stream);
+    }
     if (r->gx)
         (void)hipGraphExecDestroy(r->gx);
     if (r->g)
@@ -1419,6 +1437,7 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     }
     info->total_events = tot;
     info->first_window = run->n_launch > 1 ? run->first_window : 0;
+    info->graph = run->graph ? 1 : 0;
     return SSA_OK;
 }
 

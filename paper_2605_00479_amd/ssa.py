@@ -55,7 +55,7 @@ class ssa_run_info(ctypes.Structure):
     _fields_ = [("elapsed_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("n_launches", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("grid_size", ctypes.c_int32), ("vgprs", ctypes.c_int32),
-                ("total_events", ctypes.c_uint64), ("first_window", ctypes.c_int32)]
+                ("total_events", ctypes.c_uint64), ("first_window", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class ssa_tune_result(ctypes.Structure):

@@ -128,4 +128,23 @@ def test_negative_initial_count_rejected():
 def test_kernels_compile_for_every_mode(mode):
     W = wl.config_heterogeneous(100)
     items = ssa.items_from_workload(W)
-    ssa.ssa_prepare(items, W.t_end, W.snap_t, mode)
+    ssa.ssa_prepare(items, W.t_end, W.snap_t, mode, max_events=W.max_events)
+
+
+@pytest.mark.parametrize("mode", ["FP32", "MIX_F16_SR", "MIX_BF16_RTN", "UNI_BF16_RTN", "UNI_F16_SR_NORM"])
+def test_clocks_that_can_stall_need_an_event_cap(mode):
+    """A binary32 or 16-bit clock stops advancing once the waiting time is
+    below half its spacing: a run in such a mode must name a finite cap. The
+    run is refused before anything reaches a GPU (ssa_ensemble_run validates
+    first), so this needs none."""
+    m = ssa.Model(wl.birth_death())
+    items = [{"model": m, "x0": [0], "n_traj": 10}]
+    for fn in ("ssa_prepare", "ssa_ensemble_run"):
+        d, keep = ssa._desc(items, 1.0, [1.0], 1, mode, max_events=0)
+        args = [ctypes.byref(d)] + ([ctypes.byref(ctypes.c_void_p())] if fn == "ssa_ensemble_run" else [])
+        assert getattr(ssa.lib(), fn)(*args) == ssa.SSA_E_INVALID, fn
+        assert b"max_events" in ssa.lib().ssa_last_error()
+    d, keep = ssa._desc(items, 1.0, [1.0], 1, mode, max_events=1000)
+    assert ssa.lib().ssa_prepare(ctypes.byref(d)) == ssa.SSA_OK
+    d, keep = ssa._desc(items, 1.0, [1.0], 1, "FP64", max_events=0)
+    assert ssa.lib().ssa_prepare(ctypes.byref(d)) == ssa.SSA_OK

@@ -38,8 +38,14 @@ def assert_parity(orc_res, snap, stats, mode, label=""):
     assert np.all((a == b) | (rel <= tol_for(mode))), f"t_last {label} {mode}: max rel {rel.max()}"
 
 
+# Event cap of test runs that name none: far above any test trajectory's count
+# (a binary32 or 16-bit clock needs a finite cap, the library refuses none)
+TEST_CAP = 50_000_000
+
+
 def run_both(gpu, orc, spec, x0, n, t_end, snap_t, mode, *, seed=1, max_events=0, set_rate=None,
              traj_per_set=0, indices=None, **launch):
+    max_events = max_events or TEST_CAP
     m = gpu.Model(spec)
     item = {"model": m, "x0": x0, "n_traj": n}
     if set_rate is not None:
@@ -189,10 +195,10 @@ def run_records(gpu, orc, spec, x0, n, t_end, snap_t, mode, mask, cap, *, seed=1
     m = gpu.Model(spec)
     item = {"model": m, "x0": x0, "n_traj": n, "record": (mask, cap)}
     print(f"[gpu-parity] records {spec.name} mode={mode} n={n} mask={mask} cap={cap} launch={launch}", flush=True)
-    run = gpu.ssa_ensemble_run([item], t_end, snap_t, seed, mode, **launch)
+    run = gpu.ssa_ensemble_run([item], t_end, snap_t, seed, mode, max_events=TEST_CAP, **launch)
     rec = run.records(0)
     ref = orc.simulate(spec, mode, x0, t_end, snap_t, seed, n_traj=n, record_mask=mask, record_cap=cap,
-                       threads=ORACLE_THREADS)
+                       max_events=TEST_CAP, threads=ORACLE_THREADS)
     assert_parity(ref, run.snapshots(0), run.stats(0), mode, spec.name)
     np.testing.assert_array_equal(rec["n"], ref["rec_n"])
     for i in range(n):
@@ -290,6 +296,30 @@ def test_chunked_graph_run_matches_single_launch(gpu, orc):
             np.testing.assert_array_equal(s1, s4)
             for k in st1:
                 np.testing.assert_array_equal(st1[k], st4[k])
+
+
+@pytest.mark.parametrize("mode,launch", [("FP64", {}), ("MIX_F16_SR", {}), ("FP64", {"block_size": 512}),
+                                         ("MIX_F16_SR", {"block_size": 512})])
+def test_graph_captured_chunks(gpu, orc, mode, launch):
+    """More than 16 snapshot windows: the run's launches (the simulation
+    kernel per window and the reorder kernels between windows) are captured
+    into one hipGraph and launched as a graph. 25 windows over 51 rows, with
+    a short first window and with even windows; results equal the single
+    launch's and the oracle's."""
+    W = wl.config_schlogl()
+    it = W.items[0]
+    ts = wl.snapshot_grid(5.0, 51)
+    run1, s1, st1 = run_both(gpu, orc, it.model, it.x0, 900, 5.0, ts, mode, seed=6, max_events=W.max_events,
+                             **launch)
+    assert run1.info()["graph"] == 0
+    for chunks, window, reorder in ((25, 0, 0), (25, 3, 0), (17, 0, -1), (50, 2, 0)):
+        run, s, st = run_both(gpu, orc, it.model, it.x0, 900, 5.0, ts, mode, seed=6, max_events=W.max_events,
+                              n_chunks=chunks, first_window=window, reorder=reorder, **launch)
+        info = run.info()
+        assert info["graph"] == 1 and info["n_launches"] == chunks, info
+        np.testing.assert_array_equal(s1, s)
+        for k in st1:
+            np.testing.assert_array_equal(st1[k], st[k])
 
 
 def test_special_statuses(gpu, orc):
