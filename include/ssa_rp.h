@@ -183,7 +183,23 @@ typedef struct ssa_item {
  *     each trajectory's event rate, so that with reorder the longest
  *     trajectories start first in the next window. Must leave at least one row
  *     for every later window (else SSA_E_INVALID). With n_chunks = 0 the
- *     autotuned value is used. */
+ *     autotuned value is used.
+ *   placement: SSA_PLACE_AUTO, or SSA_PLACE_EXPLICIT | SSA_PLACE_* flags
+ *     (else SSA_E_INVALID). Results do not depend on it: draws are keyed by
+ *     trajectory id, not by lane. */
+/* Placement of work in a launch (ssa_run_desc.placement). */
+#define SSA_PLACE_AUTO 0               /* the autotuned choice if stored, else none of the flags */
+#define SSA_PLACE_EXPLICIT 1           /* the flags below are the caller's choice            */
+#define SSA_PLACE_NEIGHBOUR_PRODUCER 2 /* 512-thread workgroups: event-loop wave c takes its
+                                          draws from the producer on the next SIMD (mod 4),
+                                          so a wave left running alone has its SIMD to itself */
+#define SSA_PLACE_WAVE_MAJOR 4         /* single-item runs: each launch's first claims are
+                                          static, wave-major (the first 64 claims of the
+                                          claim order go to wave 0 of workgroup 0, the next
+                                          to wave 0 of workgroup 1, ...), so after a
+                                          reordering window the heaviest trajectories share
+                                          one wave per workgroup                            */
+
 typedef struct ssa_run_desc {
     const ssa_item *items;
     int32_t n_items;
@@ -203,6 +219,7 @@ typedef struct ssa_run_desc {
     int32_t grid_size;
     int32_t reorder;
     int32_t first_window;
+    int32_t placement;
 } ssa_run_desc;
 
 /* Start an ensemble run; returns once the work is queued on hip_stream
@@ -246,6 +263,7 @@ typedef struct ssa_run_info {
     uint64_t total_events;    /* sum of events over all trajectories */
     int32_t first_window;     /* snapshot rows of the first launch (0: even windows) */
     int32_t graph;            /* 1 if the launches ran as one captured hipGraph */
+    int32_t placement;        /* SSA_PLACE_EXPLICIT | SSA_PLACE_* flags the launches used */
 } ssa_run_info;
 
 /* Fill info for a run (waits for it). */
@@ -257,6 +275,7 @@ typedef struct ssa_tune_result {
     int32_t grid_size;    /* workgroups: sets waves per CU and trajectories per lane */
     int32_t n_chunks;     /* snapshot windows (one launch each) */
     int32_t first_window; /* snapshot rows of the first window (0: even windows) */
+    int32_t placement;    /* SSA_PLACE_EXPLICIT | chosen SSA_PLACE_* flags */
     int32_t n_candidates; /* launch shapes timed */
     double best_ms;       /* device time of the chosen shape */
 } ssa_tune_result;

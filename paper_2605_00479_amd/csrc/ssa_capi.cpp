@@ -311,13 +311,14 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
     o << "typedef " << ms.policy() << " PrecRun;\n"
       << "extern \"C\" __global__ void __launch_bounds__(256) ssa_kernel(LaunchArgs L) {\n"
       << "  const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;\n"
+      << "  const u32 slot_rank = (threadIdx.x >> 6) * gridDim.x + blockIdx.x, n_slots = gridDim.x * (blockDim.x >> 6);\n"
       << "  SelfFeed feed;\n"
       << "  u32 it = wave % SSA_N_ITEMS;\n"
       << "  for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "    switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
         o << "    case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
-          << ">(L, L.item[" << i << "], feed); break;\n";
+          << ">(L, L.item[" << i << "], feed, slot_rank, n_slots); break;\n";
     o << "    default: break;\n"
       << "    }\n"
       << "    it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
@@ -328,21 +329,25 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
     o << "constexpr int SSA_RING_NW = ";
     for (size_t i = 0; i < models.size(); ++i)
         o << (i ? ", " : "") << (i + 1 < models.size() ? "cmax(" : "")
-          << "DrawIO<PrecRun, Slots<PrecRun, Md" << i << ">::NSLOT>::NW";
+          << "RingWords<PrecRun, Md" << i << ">::NW";
     for (size_t i = 1; i < models.size(); ++i)
         o << ")";
     o << ";\n"
       << "constexpr int SSA_RING_D = ring_depth(SSA_RING_NW);\n"
       << "extern \"C\" __global__ void __launch_bounds__(512) ssa_kernel_pc(LaunchArgs L) {\n"
-      << "  const u32 w = threadIdx.x >> 6, c = w & 3u, lane = lane_id();\n"
+      << "  const u32 w = threadIdx.x >> 6, lane = lane_id();\n"
+      << "  // event-loop wave c (= w for w < 4) is fed by the producer wave on its own\n"
+      << "  // SIMD (w = c + 4) or, with PLACE_NEIGHBOUR, on the next one (w = 4 + (c + 1) % 4)\n"
+      << "  const u32 c = w < 4u ? w : ((w + ((L.place & PLACE_NEIGHBOUR) ? 3u : 0u)) & 3u);\n"
       << "  if constexpr (SSA_RING_D == 0) {\n"
       << "    SelfFeed feed;\n"
+      << "    const u32 slot_rank = w * gridDim.x + blockIdx.x, n_slots = gridDim.x * 8u;\n"
       << "    u32 it = (blockIdx.x * 8u + w) % SSA_N_ITEMS;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
         o << "      case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
-          << ">(L, L.item[" << i << "], feed); break;\n";
+          << ">(L, L.item[" << i << "], feed, slot_rank, n_slots); break;\n";
     o << "      default: break;\n"
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
@@ -352,6 +357,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  __shared__ RingCtl ctl[4];\n"
       << "  __shared__ u32 ring[4 * (SSA_RING_D > 0 ? SSA_RING_D : 1) * SSA_RING_NW * 64];\n"
       << "  if (w < 4) {\n"
+      << "    ctl[c].convw[lane] = 0u;\n"
       << "    ctl[c].req_e[lane] = 0u;\n"
       << "    ctl[c].done[lane] = 0u;\n"
       << "    ctl[c].item = 0u;\n"
@@ -363,14 +369,15 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
       << "  if (w < 4) {\n"
       << "    __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, 0u};\n"
+      << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"
       << "      lgkm_wait();\n"
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
         o << "      case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
-          << ">(L, L.item[" << i << "], feed); break;\n";
+          << ">(L, L.item[" << i << "], feed, slot_rank, n_slots); break;\n";
     o << "      default: break;\n"
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
@@ -550,7 +557,7 @@ int get_kernel(const std::string &src, Loaded &out)
 // Launch shapes chosen by ssa_autotune, keyed by the kernel source and the
 // workload's shape, kept in memory and appended to <cache dir>/tune.txt.
 struct Tuned {
-    int block = 0, grid = 0, chunks = 0, window = 0;
+    int block = 0, grid = 0, chunks = 0, window = 0, place = 0;
     double ms = 0.0;
 };
 
@@ -578,7 +585,7 @@ void tune_load_locked()
         std::istringstream ls(line);
         std::string key;
         Tuned t;
-        if (ls >> key >> t.block >> t.grid >> t.chunks >> t.window >> t.ms)
+        if (ls >> key >> t.block >> t.grid >> t.chunks >> t.window >> t.ms >> t.place)
             g_tuned[key] = t;
     }
 }
@@ -602,7 +609,8 @@ void tune_store(const std::string &key, const Tuned &t)
     ::mkdir(cache_dir().c_str(), 0755);
     std::ofstream out(cache_dir() + "/tune.txt", std::ios::app);
     if (out)
-        out << key << " " << t.block << " " << t.grid << " " << t.chunks << " " << t.window << " " << t.ms << "\n";
+        out << key << " " << t.block << " " << t.grid << " " << t.chunks << " " << t.window << " " << t.ms << " "
+            << t.place << "\n";
 }
 
 // ------------------------------------------------------------------ launch arguments
@@ -643,6 +651,7 @@ struct LaunchArgsHead {
     int32_t k_lo, k_hi;
     int32_t first, last;
     uint32_t seed_lo, seed_hi;
+    uint32_t place, place_pad;
     uint64_t max_events;
 };
 
@@ -714,6 +723,10 @@ int validate_desc(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "reorder must be -1, 0 or 1");
     if (d->first_window < 0)
         return fail(SSA_E_INVALID, "first_window must be >= 0");
+    if (d->placement != 0 && (!(d->placement & SSA_PLACE_EXPLICIT) ||
+                              (d->placement & ~(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER |
+                                                SSA_PLACE_WAVE_MAJOR)) != 0))
+        return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
     uint64_t total = 0;
@@ -804,6 +817,7 @@ struct ssa_run {
     int n_launch = 0;
     int first_window = 0;  // snapshot rows of the first chunk (0: even windows)
     int block = 0, grid = 0, vgprs = -1;
+    int place = 0;        // PLACE_* bits of the launches
     bool graph = false;
     std::vector<ItemBuf> items;
     std::vector<std::pair<void *, size_t>> owned;  // library-owned device buffers (returned to the cache)
@@ -927,6 +941,7 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
     A.h.seed_lo = (uint32_t)d->seed;
     A.h.seed_hi = (uint32_t)(d->seed >> 32);
     A.h.max_events = d->max_events;
+    A.h.place = (uint32_t)r->place;
     const int nI = d->n_items;
     hipStream_t s = r->graph ? r->cap : r->stream;
     // one zeroed counter per (chunk, item)
@@ -1027,7 +1042,7 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
 
     // launch shape chosen by ssa_autotune for this kernel and workload, if any
     Tuned tuned;
-    const bool have_tuned = (d->block_size == 0 || d->grid_size == 0 || d->n_chunks == 0) &&
+    const bool have_tuned = (d->block_size == 0 || d->grid_size == 0 || d->n_chunks == 0 || d->placement == 0) &&
                             tune_lookup(tune_key(d, src), tuned);
     const bool wide = d->format == SSA_FMT_FP64;
     int n_chunks = d->n_chunks == 0 ? (have_tuned ? tuned.chunks : 1) : d->n_chunks;
@@ -1178,6 +1193,13 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
                                 : (have_tuned && tuned.block == r->block ? tuned.grid
                                                                           : std::max<int64_t>(1, std::min(need, resident)));
     r->grid = (int)grid;
+    // placement bits: explicit (placement = SSA_PLACE_EXPLICIT | flags), else
+    // the autotuned choice where the tuned block size is the one launched
+    if (d->placement != 0)
+        r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR);
+    else if (have_tuned && tuned.block == r->block)
+        r->place = tuned.place;
+    r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0);
 
     HIP_TRY(hipEventCreate(&r->ev0));
     HIP_TRY(hipEventCreate(&r->ev1));
@@ -1438,6 +1460,8 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     info->total_events = tot;
     info->first_window = run->n_launch > 1 ? run->first_window : 0;
     info->graph = run->graph ? 1 : 0;
+    info->placement = SSA_PLACE_EXPLICIT | (run->place & 1 ? SSA_PLACE_NEIGHBOUR_PRODUCER : 0) |
+                      (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0);
     return SSA_OK;
 }
 
@@ -1465,7 +1489,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
     for (int i = 0; i < desc->n_items; ++i)
         total += desc->items[i].n_traj;
     struct Cand {
-        int block, grid, chunks, window;
+        int block, grid, chunks, window, place;
     };
     std::vector<Cand> cands;
     // one launch; 4 even windows; a first window of about a tenth of the rows
@@ -1506,7 +1530,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
         for (int64_t g : grids)
             for (const ChunkOpt &ch : chunk_opts)
-                cands.push_back({block, (int)g, ch.chunks, ch.window});
+                cands.push_back({block, (int)g, ch.chunks, ch.window, SSA_PLACE_EXPLICIT});
     }
     // 512-thread workgroups: one event-loop wave per SIMD, each paired with
     // the wave that forms its draws
@@ -1516,14 +1540,22 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         if (per_cu >= 1) {
             const int64_t need = std::max<int64_t>(1, (total + 255) / 256);
             const int64_t g = std::min<int64_t>(need, cus);
-            for (const ChunkOpt &ch : chunk_opts)
-                cands.push_back({512, (int)g, ch.chunks, ch.window});
+            // producers on their own or the next SIMD; claims as they come, or
+            // the first ones wave-major (one launch per item only)
+            std::vector<int> places = {SSA_PLACE_EXPLICIT, SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER};
+            if (desc->n_items == 1) {
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_WAVE_MAJOR);
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR);
+            }
+            for (int pl : places)
+                for (const ChunkOpt &ch : chunk_opts)
+                    cands.push_back({512, (int)g, ch.chunks, ch.window, pl});
         }
     }
     cands.erase(std::unique(cands.begin(), cands.end(),
                             [](const Cand &a, const Cand &b) {
                                 return a.block == b.block && a.grid == b.grid && a.chunks == b.chunks &&
-                                       a.window == b.window;
+                                       a.window == b.window && a.place == b.place;
                             }),
                 cands.end());
     Tuned best;
@@ -1545,6 +1577,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         d2.grid_size = c.grid;
         d2.n_chunks = c.chunks;
         d2.first_window = c.window;
+        d2.placement = c.place;
         ssa_run *r = new (std::nothrow) ssa_run;
         if (!r)
             return fail(SSA_E_NOMEM, "out of host memory");
@@ -1567,6 +1600,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
             best.grid = c.grid;
             best.chunks = c.chunks;
             best.window = c.window;
+            best.place = c.place & ~SSA_PLACE_EXPLICIT;
             best.ms = ms;
         }
     }
@@ -1576,6 +1610,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
         res->grid_size = best.grid;
         res->n_chunks = best.chunks;
         res->first_window = best.window;
+        res->placement = SSA_PLACE_EXPLICIT | best.place;
         res->best_ms = best.ms;
         res->n_candidates = (int32_t)cands.size();
     }

@@ -525,9 +525,24 @@ struct LaunchArgs {
     i32 k_lo, k_hi;          // snapshot rows written by this launch
     i32 first, last;         // first / last chunk of the run
     u32 seed_lo, seed_hi;
+    u32 place;               // PLACE_* bits (512-thread and single-item launches)
+    u32 place_pad;
     u64 max_events;          // 0 = no cap
     ItemArgs item[SSA_N_ITEMS];
 };
+
+// Placement of work in a launch.
+//   PLACE_NEIGHBOUR: in a 512-thread workgroup the draws of event-loop wave c
+//     come from the producer wave on SIMD (c + 1) mod 4 instead of its own
+//     SIMD (waves w and w + 4 share a SIMD), so an event-loop wave whose
+//     neighbours have drained runs with its SIMD to itself.
+//   PLACE_WAVE_MAJOR: single-item launches take their first claims
+//     statically, wave-major: claim slot r = c * gridDim.x + blockIdx.x of
+//     event-loop wave c in its workgroup holds claims [64 r, 64 r + 64) of
+//     the claim order (heaviest first after a reordering window), so the
+//     heaviest trajectories sit on wave 0 of every workgroup; the work
+//     counter starts past the static claims.
+enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u };
 
 enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
 
@@ -646,6 +661,23 @@ struct DrawIO {
     }
 };
 
+// Conversion fields a producer may carry in a ring slot, after the draw's own
+// words: models whose count conversions round stochastically (R13: drawn
+// only when a count exceeds the exact-integer limit). Bit 31 of the third
+// pool word marks a draw whose slot holds them.
+template <class P, class Md>
+struct ConvRing {
+    static constexpr bool ON = P::SR && !P::SELECTIVE && Md::NCONV > 0;
+    static constexpr int NW = ON ? 4 * ConvPool<Md::NCONV, P::SR_B>::NSTREAM : 0;
+    static constexpr u32 MARK = 0x80000000u;
+};
+
+// Words of one ring slot for a model: the draw, then its conversion fields.
+template <class P, class Md>
+struct RingWords {
+    static constexpr int NW = DrawIO<P, Slots<P, Md>::NSLOT>::NW + ConvRing<P, Md>::NW;
+};
+
 // --------------------------------------------------------------------------
 // Draw feeds. The event loop takes event n + 1's draw while it runs event n.
 // SelfFeed forms it in the same wave. RingFeed takes it from a ring in LDS
@@ -665,6 +697,10 @@ struct DrawIO {
 //   made   producer -> consumer: counter word of the first draw not made yet;
 //          draws [made - D, made) of epoch e are in the ring (the consumer
 //          resets it at a claim, before publishing the epoch).
+//   convw  consumer -> producer: the lane's counts need conversion fields
+//          (reset at a claim); the producer then also forms each draw's
+//          conversion fields, stores them after the draw's words, and marks
+//          the draw by bit 31 of its third pool word (a bit no field uses).
 // The producer writes draw p only while p < done + D, so a draw the consumer
 // finds made stays in place until it has read it. Ordering rests on waits for
 // completed LDS operations (lgkmcnt 0): the producer waits for its ring
@@ -678,6 +714,7 @@ struct RingCtl {
     u32 req_id[64];
     u32 req_lo[64];
     u32 req_hi[64];
+    u32 convw[64];   // consumer -> producer: 1 while the lane's trajectory wants conversion fields
     u32 item;        // consumer -> producer: sequence number of the item in progress (~0u: finished)
 };
 
@@ -711,6 +748,7 @@ struct RingFeed {
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
     u32 dw;         // counter word of the draw the lane takes next (event n + 1)
+    u32 cflag;      // the lane has asked its producer for conversion fields
 
     // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
     // made is reset to "nothing made in this epoch" before the epoch is
@@ -725,8 +763,41 @@ struct RingFeed {
         lds_st(&ctl->req_id[lane], id);
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
+        lds_st(&ctl->convw[lane], 0u);
+        cflag = 0u;
         lgkm_wait();
         lds_st(&ctl->req_e[lane], eb);
+    }
+
+    // Conversion fields of the current event's draw (event n, counter word
+    // dw - 256): from its ring slot where the producer formed them with the
+    // draw (the draw came from the ring and carries the mark), formed here
+    // for the lanes that need them otherwise. need: this lane's counts exceed
+    // the exact-integer limit (only then do its fields matter); it also asks
+    // the producer to form them for the rest of the trajectory. The slot is
+    // intact: the producer may rewrite it only once done passes event n, which
+    // read() publishes after this event's loads have completed.
+    template <int NCONV, int B, int OFF>
+    __device__ ConvPool<NCONV, B> conv(u32 mark, bool need, u64 act, u64 n, u32 id, u32 k0, u32 k1)
+    {
+        ConvPool<NCONV, B> cp;
+        const u32 *sl = (const u32 *)((const char *)(ring + lane) + ((dw - 256u) & (u32)((D - 1) << 8)));
+#pragma unroll
+        for (int q = 0; q < ConvPool<NCONV, B>::NSTREAM * 4; ++q)
+            cp.w[q] = sl[(OFF + q) * D * 64];
+        if (need && !cflag) {
+            lds_st(&ctl->convw[lane], 1u);
+            cflag = 1u;
+        }
+        const bool have = (mark & 0x80000000u) != 0u;
+        const u64 self = act & lanes(need) & ~lanes(have);
+        if (__builtin_expect(self != 0, 0)) {
+            __asm__ volatile("");
+            const ConvPool<NCONV, B> f = make_conv<NCONV, B>(n, id, k0, k1);
+            if (!have)
+                cp = f;
+        }
+        return cp;
     }
 
     __device__ u32 made_word() const { return lds_ld(&ctl->made[lane]); }
@@ -789,6 +860,8 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 {
     typedef Slots<P, Md> S;
     typedef DrawIO<P, S::NSLOT> IO;
+    typedef ConvRing<P, Md> CR;
+    static_assert(!CR::ON || IO::NP >= 3, "the conversion mark lives in the third pool word");
     constexpr int BATCH = D >= 16 ? (P::WIDE ? 8 : 6) : (D >= 2 ? D / 2 : 1);
     constexpr int START = P::WIDE && BATCH > 4 ? 4 : BATCH;
     const u32 lane = lane_id();
@@ -799,6 +872,9 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
         lgkm_wait();   // a new epoch's request words were written before it
         const u32 item = __builtin_amdgcn_readfirstlane(lds_ld(&ctl->item));
         const u32 dw = lds_ld(&ctl->done[lane]);
+        u32 cw = 0u;
+        if constexpr (CR::ON)
+            cw = lds_ld(&ctl->convw[lane]);
         if (item != seq)
             break;
         if (re != e) {
@@ -833,6 +909,32 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 #pragma unroll
                 for (int k = 0; k < IO::NP; ++k)
                     __asm__ volatile("" : "+v"(d[b].pool.w[k]));
+            }
+        }
+        // conversion fields of the batch, where some lane of the wave asked
+        // for them: formed for every lane, marked in each draw, stored after
+        // the draw's words
+        if constexpr (CR::ON) {
+            if (__builtin_amdgcn_ballot_w64(mine && cw != 0u) != 0) {
+                ConvPool<Md::NCONV, P::SR_B> cv[BATCH];
+#pragma unroll
+                for (int b = 0; b < BATCH; ++b)
+                    cv[b] = make_conv<Md::NCONV, P::SR_B>(p + (u64)b, id, L.seed_lo, L.seed_hi);
+#pragma unroll
+                for (int b = 0; b < BATCH; ++b) {
+#pragma unroll
+                    for (int q = 0; q < CR::NW; ++q)
+                        __asm__ volatile("" : "+v"(cv[b].w[q]));
+                    d[b].pool.w[2] |= CR::MARK;
+                }
+#pragma unroll
+                for (int b = 0; b < BATCH; ++b)
+                    if ((u32)b < room) {
+                        u32 *w = ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * 64 + lane;
+#pragma unroll
+                        for (int q = 0; q < CR::NW; ++q)
+                            w[(IO::NW + q) * D * 64] = cv[b].w[q];
+                    }
             }
         }
 #pragma unroll
@@ -872,7 +974,7 @@ __host__ __device__ constexpr int cmax(int a, int b)
 // Md: generated network description; P: precision policy.
 // --------------------------------------------------------------------------
 template <class P, class Md, bool PER_LANE_RATES, class F>
-__device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
+__device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 slot_rank, u32 n_slots)
 {
     typedef typename P::T T;
     typedef typename P::A A;
@@ -917,6 +1019,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
             c[j] = uniform_value(rates[j]);
     }
 
+    // wave-major static first claim (single-item launches): every lane is idle
+    // at the start, so the wave's claim is its slot's 64 consecutive claims
+    bool static_claim = SSA_N_ITEMS == 1 && (L.place & PLACE_WAVE_MAJOR) != 0u;
+    const u32 dyn_base = static_claim ? n_slots * 64u : 0u;   // claims after the static ones
     for (;;) {
         if (open) {
             u64 need = __ballot(!active);
@@ -924,9 +1030,14 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                 u32 cnt = (u32)__popcll(need);
                 u32 leader = (u32)__ffsll((long long)need) - 1u;
                 u32 base = 0;
-                if (lane == leader)
-                    base = atomicAdd(I.counter, cnt);
-                base = __builtin_amdgcn_readlane(base, leader);
+                if (static_claim) {
+                    base = slot_rank * 64u;
+                    static_claim = false;
+                } else {
+                    if (lane == leader)
+                        base = atomicAdd(I.counter, cnt);
+                    base = __builtin_amdgcn_readlane(base, leader) + dyn_base;
+                }
                 if (!active) {
                     u32 w = base + rank_in(need);
                     if (w < I.E) {
@@ -1038,8 +1149,12 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed)
                             // the empty asm keeps this a branch: merged with the exact
                             // version, the conversion stream would be drawn every event
                             __asm__ volatile("");
-                            const ConvPool<Md::NCONV, P::SR_B> cpool =
-                                make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
+                            ConvPool<Md::NCONV, P::SR_B> cpool;
+                            if constexpr (F::RING)   // from the producer where it formed them
+                                cpool = feed.template conv<Md::NCONV, P::SR_B, DrawIO<P, NSLOT>::NW>(
+                                    cur.pool.w[2], mx > (u32)P::EXACT_INT, act, n, id, L.seed_lo, L.seed_hi);
+                            else
+                                cpool = make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
                             Md::template propensities<P, false, true>(x, c, hill, a, pool, cpool);
                         }
                     }

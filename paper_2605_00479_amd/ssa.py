@@ -48,19 +48,21 @@ class ssa_run_desc(ctypes.Structure):
                 ("rounding", ctypes.c_int32), ("norm", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("max_events", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
                 ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("reorder", ctypes.c_int32),
-                ("first_window", ctypes.c_int32)]
+                ("first_window", ctypes.c_int32), ("placement", ctypes.c_int32)]
 
 
 class ssa_run_info(ctypes.Structure):
     _fields_ = [("elapsed_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
                 ("n_launches", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("grid_size", ctypes.c_int32), ("vgprs", ctypes.c_int32),
-                ("total_events", ctypes.c_uint64), ("first_window", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("total_events", ctypes.c_uint64), ("first_window", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("placement", ctypes.c_int32)]
 
 
 class ssa_tune_result(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
-                ("first_window", ctypes.c_int32), ("n_candidates", ctypes.c_int32), ("best_ms", ctypes.c_double)]
+                ("first_window", ctypes.c_int32), ("placement", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("best_ms", ctypes.c_double)]
 
 
 EXPORTS = ("ssa_autotune", "ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
@@ -206,7 +208,7 @@ class Run:
 
 
 def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,
-          block_size=0, grid_size=0, reorder=0, first_window=0, stream=None, outputs=None):
+          block_size=0, grid_size=0, reorder=0, first_window=0, placement=0, stream=None, outputs=None):
     """Build an ssa_run_desc. items: list of dicts with model (Model), x0, n_traj,
     optional set_rates [n_sets, M] and traj_per_set, optional record =
     (reaction mask, records per trajectory)."""
@@ -260,11 +262,16 @@ def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_c
     d.grid_size = int(grid_size)
     d.reorder = int(reorder)
     d.first_window = int(first_window)
+    d.placement = int(placement)
     return d, keep
 
 
+PLACE_AUTO, PLACE_EXPLICIT, PLACE_NEIGHBOUR_PRODUCER, PLACE_WAVE_MAJOR = 0, 1, 2, 4
+
+
 def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,
-                     block_size=0, grid_size=0, reorder=0, first_window=0, torch_outputs=True) -> Run:
+                     block_size=0, grid_size=0, reorder=0, first_window=0, placement=0,
+                     torch_outputs=True) -> Run:
     """Queue an ensemble run on torch's current stream. With torch_outputs the
     device outputs are torch tensors owned by the returned Run."""
     import torch
@@ -289,7 +296,7 @@ def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_
     stream = torch.cuda.current_stream().cuda_stream
     d, keep = _desc(items, t_end, snap_t, seed, mode, max_events=max_events, traj_id_base=traj_id_base,
                     n_chunks=n_chunks, block_size=block_size, grid_size=grid_size, reorder=reorder,
-                    first_window=first_window, stream=stream, outputs=outputs)
+                    first_window=first_window, placement=placement, stream=stream, outputs=outputs)
     h = ctypes.c_void_p()
     _check(lib().ssa_ensemble_run(ctypes.byref(d), ctypes.byref(h)))
     meta = [(it["model"].n_species, int(it["n_traj"]), K) for it in items]

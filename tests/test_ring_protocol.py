@@ -12,6 +12,13 @@ its current trajectory and event. Runs cover slow and fast producers, short
 trajectories that cycle the 255 epochs many times, event indices crossing the
 24-bit wrap, and a producer that sees claims late (it then skips ahead).
 
+Conversion fields: a lane whose counts pass the exact-integer limit sets its
+request word; the producer then also forms each draw's conversion fields into
+the slot and marks the draw. In an event that needs them the lane reads the
+current draw's fields from its slot (before it publishes done) if that draw
+came from the ring with the mark, and forms them itself otherwise; fields it
+reads must be its own draw's.
+
 This checks the protocol as designed; the GPU tests check the kernel's results.
 """
 import random
@@ -45,11 +52,15 @@ class Shared:
         self.req_id = 0
         self.req_lo = 0
         self.req_hi = 0
-        self.ring = [None] * D
+        self.convw = 0
+        self.ring = [None] * D      # (trajectory, event) of the draw
+        self.conv = [None] * D      # (trajectory, event) of the conversion fields
 
 
-def consumer(sh, D, rng, n_traj, start_n, log, lengths):
-    """Generator: one step per LDS operation (plus the local work between)."""
+def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
+    """Generator: one step per LDS operation (plus the local work between).
+    p_need: per trajectory, the chance that its counts pass the exact-integer
+    limit (from a random event on, until it ends)."""
     eb = 0
     for uid in range(1, n_traj + 1):     # uid: the trajectory's id (draws are keyed by it)
         n = start_n(rng)
@@ -62,14 +73,30 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths):
         sh.made = dw
         yield
         sh.req_id, sh.req_lo, sh.req_hi = uid, n & 0xFFFFFFFF, n >> 32
+        sh.convw = 0
+        cflag = False
         yield
         sh.req_e = eb
         yield
         length = lengths(rng)
-        for _ in range(length):
+        need_from = rng.randint(0, max(length, 1)) if rng.random() < p_need else None
+        cur_mark = False                                      # the claim forms its draw itself
+        for ev in range(length):
             want = n + 1
             mw = sh.made                                      # top of the event
             yield
+            if need_from is not None and ev >= need_from:     # conversion path: fields of draw n
+                fields = sh.conv[(((dw - 256) & M32) >> 8) % D]
+                yield
+                if not cflag:
+                    sh.convw = 1
+                    cflag = True
+                    yield
+                if cur_mark:
+                    log["conv_ring"] += 1
+                    assert fields == (uid, n), f"stale conversion fields: got {fields}, wanted {(uid, n)}"
+                else:
+                    log["conv_self"] += 1
             sh.done = dw                                      # after the wait: done, then ring words
             yield
             data = sh.ring[(dw >> 8) % D]
@@ -79,9 +106,11 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths):
             dw = nxt
             if hit:
                 log["hits"] += 1
-                assert data == (uid, want), f"stale draw: got {data}, wanted {(uid, want)}"
+                assert data is not None and data[:2] == (uid, want), f"stale draw: got {data}, wanted {(uid, want)}"
+                cur_mark = data[2]
             else:
                 log["misses"] += 1                            # formed by the lane itself
+                cur_mark = False
             n = want                                          # the event fires
     log["consumer_done"] = True
 
@@ -100,6 +129,8 @@ def producer(sh, D, batch, rng, log, skip=True, start=1):
             uid = sh.req_id
             p = ((sh.req_hi << 32) | sh.req_lo) + 1
             yield
+        cw = sh.convw
+        yield
         mine = e != 0 and (dw & 0xFF) == e
         if skip:
             ahead = sra8((p << 8) - (dw & ~0xFF))
@@ -113,8 +144,12 @@ def producer(sh, D, batch, rng, log, skip=True, start=1):
             yield                                             # sleep
             continue
         k = min(room, batch)
+        mark = bool(mine and cw)
         for b in range(k):
-            sh.ring[(p + b) % D] = (uid, p + b)
+            if mark:
+                sh.conv[(p + b) % D] = (uid, p + b)
+                yield
+            sh.ring[(p + b) % D] = (uid, p + b, mark)
             yield
         sh.made = word(p + k, e)                              # after the wait for the stores
         yield
@@ -127,14 +162,14 @@ def mixed_lengths(r):
 
 
 def run(seed, D=16, batch=8, p_producer=0.5, n_traj=300, start=None, skip=True, lengths=mixed_lengths,
-        hold_after_claim=0, batch_start=1):
+        hold_after_claim=0, batch_start=1, p_need=0.0):
     """hold_after_claim: the producer does not run for that many steps after each
     claim (it sees the claim late, after the lane has formed draws itself)."""
     rng = random.Random(seed)
     sh = Shared(D)
-    log = {"hits": 0, "misses": 0, "made": 0, "step": 0, "claim_step": 0}
+    log = {"hits": 0, "misses": 0, "made": 0, "step": 0, "claim_step": 0, "conv_ring": 0, "conv_self": 0}
     start = start or (lambda r: r.randint(0, 50))
-    c = consumer(sh, D, rng, n_traj, start, log, lengths)
+    c = consumer(sh, D, rng, n_traj, start, log, lengths, p_need)
     pr = producer(sh, D, batch, rng, log, skip, batch_start)
     live = {"c": c, "p": pr}
     while "c" in live:
@@ -226,3 +261,43 @@ def test_a_late_producer_skips_ahead_and_keeps_up():
     fast = run(7, p_producer=0.5, n_traj=100, lengths=long_runs, hold_after_claim=40)
     stuck = run(7, p_producer=0.5, n_traj=100, lengths=long_runs, hold_after_claim=40, skip=False)
     assert fast["hits"] > 5 * max(stuck["hits"], 1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("p_producer,D,batch", [(0.5, 16, 6), (0.2, 8, 4), (0.85, 8, 4), (0.5, 2, 1)])
+def test_conversion_fields_from_the_ring_are_the_lanes_own(seed, p_producer, D, batch):
+    # trajectories that pass the exact-integer limit part way through; fields
+    # taken from the ring must be those of the lane's current draw
+    log = run(500 + seed, D=D, batch=batch, p_producer=p_producer, n_traj=400, p_need=0.6,
+              lengths=lambda r: r.choice([1, 3, r.randint(10, 80)]))
+    assert log["conv_self"] > 0
+    if p_producer >= 0.5:    # a slow producer may never get ahead of a lane's request
+        assert log["conv_ring"] > 0
+
+
+def test_conversion_fields_across_epoch_reuse():
+    # short trajectories and late claims cycle the epoch byte: a stale mark or
+    # stale fields from 255 claims earlier must never be taken
+    for seed in range(10):
+        st = {}
+        run(600 + seed, p_producer=0.5, n_traj=255 * 4 + 1, start=lambda r: 5, p_need=0.5,
+            lengths=lambda r: bursts_of_finished(r, st) or r.randint(0, 2), hold_after_claim=10)
+
+
+def test_the_mark_check_is_what_keeps_stale_fields_out():
+    # a copy of the model whose lane takes ring fields without checking the
+    # draw's mark reads fields of another draw
+    src = open(__file__).read()
+    variant = src.replace("                if cur_mark:\n                    log[\"conv_ring\"]",
+                          "                if True:\n                    log[\"conv_ring\"]")
+    assert variant != src
+    ns = {"__name__": "variant"}
+    exec(compile(variant, "variant", "exec"), ns)
+    stale = 0
+    for seed in range(6):
+        try:
+            ns["run"](500 + seed, D=8, batch=4, p_producer=0.2, n_traj=400, p_need=0.6,
+                      lengths=lambda r: r.choice([1, 3, r.randint(10, 80)]))
+        except AssertionError:
+            stale += 1
+    assert stale > 0
