@@ -52,6 +52,9 @@ def parse():
                    help="also run a 1 GiB device copy (calibrates the profiler's memory counters)")
     p.add_argument("--block", type=int, default=0)
     p.add_argument("--grid", type=int, default=0)
+    p.add_argument("--first-window", type=int, default=0)
+    p.add_argument("--placement", type=int, default=0,
+                   help="0: autotuned; else 1 | 2 (producer on the next SIMD) | 4 (wave-major first claims)")
     return p.parse_args()
 
 
@@ -69,7 +72,8 @@ def make_workload(name, n):
 
 def launch(ssa, items, W, mode, seed, args):
     return ssa.ssa_ensemble_run(items, W.t_end, W.snap_t, seed, mode, max_events=W.max_events,
-                                n_chunks=args.chunks, block_size=args.block, grid_size=args.grid)
+                                n_chunks=args.chunks, block_size=args.block, grid_size=args.grid,
+                                first_window=args.first_window, placement=args.placement)
 
 
 def marginals(run, W):
@@ -318,9 +322,10 @@ def main():
         "fidelity": fidelity,
         "fidelity_gate": "passed" if passed else ("skipped" if fidelity is None else "failed"),
         "status_counts": main_res["status_counts"],
-        "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches", "first_window")},
+        "launch": {k: main_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches", "first_window",
+                                                     "placement")},
         "launch_fp64": {k: ref_res["info"][k] for k in ("block_size", "grid_size", "vgprs", "n_launches",
-                                                          "first_window")},
+                                                          "first_window", "placement")},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
                      "unit": "TVALU-slot/s", "frac": achieved / PEAK_VALU_SLOTS,
                      "traffic": measured_traffic(W.name, args.mode, ve["file"]),

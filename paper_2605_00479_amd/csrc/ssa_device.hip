@@ -952,12 +952,15 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 }
 
 // Ring depth for draws of nw words: the largest power of two up to 16 whose
-// four rings fit 88 KiB of LDS; 0 where not even a depth of 2 fits (then the
-// 512-thread kernel runs eight event-loop waves that form their own draws).
+// four rings and four control blocks fit a workgroup's LDS (gfx950: 160 KiB
+// per CU, all of it available to one workgroup; 1 KiB is left spare); 0
+// where not even a depth of 2 fits (then the 512-thread kernel runs eight
+// event-loop waves that form their own draws).
+constexpr int kLdsBytes = 160 * 1024;
 __host__ __device__ constexpr int ring_depth(int nw)
 {
     int d = 16;
-    while (d >= 2 && 4 * d * nw * 64 * 4 > 90112)
+    while (d >= 2 && 4 * d * nw * 64 * 4 + 4 * (int)sizeof(RingCtl) > kLdsBytes - 1024)
         d /= 2;
     return d >= 2 ? d : 0;
 }
