@@ -230,6 +230,31 @@ typedef struct ssa_run_desc {
  *   combination), SSA_E_COMPILE, SSA_E_NOMEM, SSA_E_DEVICE. */
 int ssa_ensemble_run(const ssa_run_desc *desc, ssa_run **out);
 
+/* The allocation-free variant of ssa_ensemble_run, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same descriptor, same kernels, same
+ * results; differences:
+ *   - every item must bring its device outputs (d_snap unless it has no
+ *     cells, d_n_events, d_t_last, d_status; a recording item also d_rec_t,
+ *     d_rec_j, d_rec_n), else SSA_E_INVALID;
+ *   - the kernel for the run's networks and precision must already be loaded
+ *     on the current device by an earlier ssa_ensemble_run or ssa_autotune
+ *     (compiling and loading allocate), else SSA_E_INVALID;
+ *   - the run's tables, work counters, carry state and claim order live in a
+ *     fixed 64 MiB device array of the library (one per device, held until
+ *     the process ends); a run that needs more (chunked runs of very large
+ *     ensembles) gets SSA_E_INVALID. The first call on a device looks the
+ *     array's address up once;
+ *   - snapshot windows are always launched directly (no graph), and no run
+ *     handle, events or timings are made: the work is queued on
+ *     desc->hip_stream (tables copied asynchronously on it) and the results
+ *     are in the caller's buffers once that stream has passed it.
+ * Every call on one device shares that device's array: calls whose work may
+ * overlap on a device (other streams, other threads) race and must be
+ * serialised by the caller. Allocates no device memory and calls no device
+ * allocator. Errors: as ssa_ensemble_run's validation, SSA_E_DEVICE. */
+int ssa_ensemble_run_noalloc(const ssa_run_desc *desc);
+
 /* Block until the run's work on its stream is complete. SSA_E_DEVICE on a
  * HIP error. */
 int ssa_run_wait(ssa_run *run);

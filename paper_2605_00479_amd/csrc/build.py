@@ -40,7 +40,7 @@ def embed_device_source() -> str:
 
 def build_library(verbose: bool = False) -> str:
     embed_device_source()
-    cmd = ["hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", *HIP_FLAGS,
+    cmd = ["hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", *HIP_FLAGS,
            "-I", os.path.join(ROOT, "include"), "-I", BUILD,
            os.path.join(HERE, "ssa_capi.cpp"), "-o", LIB + ".tmp", "-lhiprtc", "-ldl"]
     res = subprocess.run(cmd, capture_output=True, text=True)

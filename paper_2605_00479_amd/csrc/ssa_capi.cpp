@@ -510,7 +510,9 @@ struct Loaded {
 std::mutex g_jit_mu;
 std::unordered_map<std::string, Loaded> g_loaded;  // key: device + source hash
 
-int get_kernel(const std::string &src, Loaded &out)
+// load_if_missing = false: only a kernel an earlier run loaded on this
+// device (no compilation, no module load: they allocate)
+int get_kernel(const std::string &src, Loaded &out, bool load_if_missing = true)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -522,6 +524,10 @@ int get_kernel(const std::string &src, Loaded &out)
         out = it->second;
         return SSA_OK;
     }
+    if (!load_if_missing)
+        return fail(SSA_E_INVALID, "ssa_ensemble_run_noalloc: the kernel for these networks and this precision is "
+                                   "not loaded on this device; run ssa_ensemble_run (or ssa_autotune) with them "
+                                   "once first");
     std::vector<char> code;
     int rc = compile_source(src, "gfx950", code);
     if (rc != SSA_OK)
@@ -831,6 +837,11 @@ struct ssa_run {
     double *t64 = nullptr;
     float *t32 = nullptr;
     uint32_t *counters = nullptr;
+    // runs of ssa_ensemble_run_noalloc: device buffers come from the scratch
+    // array (bump allocation), no events, no graph, no kernel compilation
+    bool noalloc = false;
+    char *scratch = nullptr;
+    size_t scratch_used = 0, scratch_cap = 0;
 };
 
 namespace {
@@ -894,6 +905,17 @@ int dalloc(ssa_run *r, T **p, size_t n)
     *p = nullptr;
     if (n == 0)
         return SSA_OK;
+    if (r->noalloc) {
+        const size_t off = (r->scratch_used + 255) & ~(size_t)255;
+        const size_t bytes = n * sizeof(T);
+        if (bytes > r->scratch_cap || off > r->scratch_cap - bytes)
+            return fail(SSA_E_INVALID, "the run needs more than the " + std::to_string(r->scratch_cap >> 20) +
+                                           " MiB scratch array of ssa_ensemble_run_noalloc (fewer snapshot "
+                                           "windows or trajectories, or use ssa_ensemble_run)");
+        r->scratch_used = off + bytes;
+        *p = (T *)(r->scratch + off);
+        return SSA_OK;
+    }
     const size_t want = cache_size_class(n * sizeof(T));
     size_t got = want;
     void *q = cache_take(r->device, want, &got);
@@ -985,11 +1007,11 @@ int launch_all(ssa_run *r, const ssa_run_desc *d, const Loaded &ld, int n_chunks
             ia.id_base = b.id_base;
         }
         void *args[] = {&A};
-        if (!r->graph)
+        if (!r->kev.empty())
             HIP_TRY(hipEventRecord(r->kev[2 * c], s));
         HIP_TRY(hipModuleLaunchKernel(r->block == 512 ? ld.kernel_pc : ld.kernel, r->grid, 1, 1, r->block, 1, 1,
                                       r->block == 512 ? ld.pc_lds_pad : 0u, s, args, nullptr));
-        if (!r->graph)
+        if (!r->kev.empty())
             HIP_TRY(hipEventRecord(r->kev[2 * c + 1], s));
         // claim order for the next chunk: heaviest trajectories of this chunk first
         if (c + 1 < n_chunks) {
@@ -1035,7 +1057,7 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     std::string src;
     build_source(d, src);
     Loaded ld;
-    int rc = get_kernel(src, ld);
+    int rc = get_kernel(src, ld, !r->noalloc);
     if (rc != SSA_OK)
         return rc;
     r->vgprs = ld.vgprs;
@@ -1163,8 +1185,12 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         char *base = nullptr;
         if ((rc = dalloc(r, &base, blob.size())))
             return rc;
-        if (!blob.empty())
-            HIP_TRY(hipMemcpy(base, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        if (!blob.empty()) {
+            if (r->noalloc)   // ordered on the run's stream after earlier work there
+                HIP_TRY(hipMemcpyAsync(base, blob.data(), blob.size(), hipMemcpyHostToDevice, r->stream));
+            else
+                HIP_TRY(hipMemcpy(base, blob.data(), blob.size(), hipMemcpyHostToDevice));
+        }
         r->t64 = (double *)(base + off_t64);
         r->t32 = (float *)(base + off_t32);
         for (int i = 0; i < d->n_items; ++i) {
@@ -1201,9 +1227,14 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
         r->place = tuned.place;
     r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0);
 
+    r->n_launch = n_chunks;
+    if (r->noalloc) {   // direct launches, no events
+        r->graph = false;
+        r->queued = true;
+        return dispatch_launch(r, d, ld, n_chunks);
+    }
     HIP_TRY(hipEventCreate(&r->ev0));
     HIP_TRY(hipEventCreate(&r->ev1));
-    r->n_launch = n_chunks;
     // A captured graph pays off only over long chunk sequences: capture and
     // instantiation cost more than a few direct launches.
     r->graph = n_chunks > kGraphMinChunks;
@@ -1267,6 +1298,34 @@ void release(ssa_run *r)
     for (auto &o : r->owned)
         cache_give(r->device, o.first, o.second);
     delete r;
+}
+
+// ------------------------------------------------------------------ scratch array
+// Device memory of ssa_ensemble_run_noalloc: tables, work counters, carry state
+// and claim order of its runs. Each device holds its own copy (from the first
+// call on it until the process ends). In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SSA_E_UNSUPPORTED, "device index beyond the library's limit");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SSA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (char *)g_scratch_ptr[dev];
+    return SSA_OK;
 }
 
 }  // namespace
@@ -1357,6 +1416,33 @@ int ssa_ensemble_run(const ssa_run_desc *desc, ssa_run **out)
     }
     *out = r;
     return SSA_OK;
+}
+
+// The allocation-free variant of ssa_ensemble_run (declared in ssa_rp.h).
+int ssa_ensemble_run_noalloc(const ssa_run_desc *desc)
+{
+    int rc = validate_desc(desc);
+    if (rc != SSA_OK)
+        return rc;
+    for (int i = 0; i < desc->n_items; ++i) {
+        const ssa_item &it = desc->items[i];
+        const size_t E = (size_t)it.n_traj;
+        const size_t cells = (size_t)desc->n_snap * it.model->m.N * E;
+        if ((cells && !it.d_snap) || (E && (!it.d_n_events || !it.d_t_last || !it.d_status)))
+            return fail(SSA_E_INVALID, "ssa_ensemble_run_noalloc: every item needs its device outputs "
+                                       "(d_snap, d_n_events, d_t_last, d_status)");
+        if (it.record_mask && it.record_cap > 0 && E && (!it.d_rec_t || !it.d_rec_j || !it.d_rec_n))
+            return fail(SSA_E_INVALID, "ssa_ensemble_run_noalloc: a recording item needs d_rec_t, d_rec_j "
+                                       "and d_rec_n");
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    ssa_run r;
+    r.noalloc = true;
+    r.scratch_cap = kScratchBytes;
+    if ((rc = scratch_address(dev, &r.scratch)) != SSA_OK)
+        return rc;
+    return run_impl(desc, &r);
 }
 
 int ssa_run_wait(ssa_run *run)

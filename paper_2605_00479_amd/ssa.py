@@ -68,7 +68,7 @@ class ssa_tune_result(ctypes.Structure):
 EXPORTS = ("ssa_autotune", "ssa_model_create", "ssa_model_destroy", "ssa_ensemble_run", "ssa_run_wait",
            "ssa_snapshots_get", "ssa_run_stats_get", "ssa_run_info_get", "ssa_run_destroy",
            "ssa_last_error", "ssa_version", "ssa_prepare", "ssa_dump_source", "ssa_kernel_file",
-           "ssa_records_get")
+           "ssa_records_get", "ssa_ensemble_run_noalloc")
 
 _lib = None
 
@@ -101,6 +101,7 @@ def lib():
         L.ssa_dump_source.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p]
         L.ssa_kernel_file.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.c_char_p, ctypes.c_size_t]
         L.ssa_autotune.argtypes = [ctypes.POINTER(ssa_run_desc), ctypes.POINTER(ssa_tune_result)]
+        L.ssa_ensemble_run_noalloc.argtypes = [ctypes.POINTER(ssa_run_desc)]
         _lib = L
     return _lib
 
@@ -302,6 +303,19 @@ def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_
     meta = [(it["model"].n_species, int(it["n_traj"]), K) for it in items]
     caps = [int(it["record"][1]) if it.get("record") is not None and int(it["record"][0]) else 0 for it in items]
     return Run(h, meta, keep, caps)
+
+
+def ssa_ensemble_run_noalloc(items, t_end, snap_t, seed, mode, outputs, **kw):
+    """Queue a run that allocates no device memory on torch's current stream.
+    outputs: per item a tuple of caller-owned device tensors (snap [K, N, E]
+    int32, n_events [E] int64, t_last [E] float64, status [E] uint8, and for
+    a recording item rec_t, rec_j, rec_n). The kernel must have been loaded by
+    an earlier ssa_ensemble_run of the same networks and precision."""
+    import torch
+    d, keep = _desc(items, t_end, snap_t, seed, mode, stream=torch.cuda.current_stream().cuda_stream,
+                    outputs=outputs, **kw)
+    _check(lib().ssa_ensemble_run_noalloc(ctypes.byref(d)))
+    return keep
 
 
 def ssa_autotune(items, t_end, snap_t, seed, mode, **kw) -> dict:
