@@ -147,6 +147,86 @@ int reaction_main_slots(const Model &md, int j)
     return L.h + (L.kind == SSA_LAW_HILL_REPRESS ? 3 : 4);
 }
 
+// Propensities for round-to-nearest fp16 (P::NATIVE16): the same op sequence
+// per reaction (a_j = c_j times its falling-factorial factors, left to right),
+// with the mass-action chains of two reactions advanced together: their k-th
+// products form one packed fp16 multiply (v_pk_mul_f16, two IEEE fp16
+// products). Reactions are paired longest chain first, so paired chains
+// share most of their steps. Hill laws are computed as in the other modes.
+std::string gen_propensities_packed(const Model &md)
+{
+    std::ostringstream o;
+    std::vector<int> ma;   // mass-action reactions with at least one factor
+    std::vector<std::vector<std::pair<int, int>>> fac((size_t)md.M);
+    for (int j = 0; j < md.M; ++j) {
+        if (md.law[j].kind != SSA_LAW_MASS_ACTION)
+            continue;
+        for (int s = 0; s < md.N; ++s)
+            for (int i = 0; i < md.order[(size_t)j * md.N + s]; ++i)
+                fac[(size_t)j].push_back({s, i});
+        if (!fac[(size_t)j].empty())
+            ma.push_back(j);
+    }
+    std::stable_sort(ma.begin(), ma.end(),
+                     [&](int a, int b) { return fac[(size_t)a].size() > fac[(size_t)b].size(); });
+    o << "      typedef _Float16 h2 __attribute__((ext_vector_type(2)));\n";
+    auto f16 = [](const std::pair<int, int> &f) {
+        return "(_Float16)P::template cvt_sub<EXACT>(x[" + std::to_string(f.first) + "], " +
+               std::to_string(f.second) + ", 0u)";
+    };
+    for (size_t p = 0; p < ma.size(); p += 2) {
+        const int j0 = ma[p];
+        if (p + 1 == ma.size()) {
+            o << "      { _Float16 r = (_Float16)c[" << j0 << "];\n";
+            for (const auto &f : fac[(size_t)j0])
+                o << "        r = r * " << f16(f) << ";\n";
+            o << "        a[" << j0 << "] = (float)r; }\n";
+            continue;
+        }
+        const int j1 = ma[p + 1];
+        const size_t n0 = fac[(size_t)j0].size(), n1 = fac[(size_t)j1].size();   // n0 >= n1
+        o << "      { h2 r = {(_Float16)c[" << j0 << "], (_Float16)c[" << j1 << "]};\n";
+        for (size_t k = 0; k < n1; ++k)
+            o << "        r = r * (h2){" << f16(fac[(size_t)j0][k]) << ", " << f16(fac[(size_t)j1][k]) << "};\n";
+        o << "        _Float16 r0 = r.x;\n";
+        for (size_t k = n1; k < n0; ++k)
+            o << "        r0 = r0 * " << f16(fac[(size_t)j0][k]) << ";\n";
+        o << "        a[" << j0 << "] = (float)r0; a[" << j1 << "] = (float)r.y; }\n";
+    }
+    for (int j = 0; j < md.M; ++j) {
+        const ssa_law &L = md.law[j];
+        if (L.kind == SSA_LAW_MASS_ACTION) {
+            if (fac[(size_t)j].empty()) {
+                o << "      a[" << j << "] = c[" << j << "];\n";
+                continue;
+            }
+            std::string zero;
+            for (int s = 0; s < md.N; ++s) {
+                int os = md.order[(size_t)j * md.N + s];
+                if (os > 0)
+                    zero += (zero.empty() ? "" : " || ") + std::string("x[") + std::to_string(s) + "] < " +
+                            std::to_string(os);
+            }
+            o << "      if (GUARD && (" << zero << ")) a[" << j << "] = (T)0;\n";
+        } else {
+            o << "      { T xr = P::template cvt<EXACT>(x[" << L.regulator << "], 0u);\n"
+              << "        T q = P::div(xr, hill[" << 2 * j + 1 << "], 0u);\n"
+              << "        T qh = q;\n";
+            for (int i = 1; i < L.h; ++i)
+                o << "        qh = P::mul(qh, q, 0u);\n";
+            o << "        T d = P::add((T)1, qh, 0u);\n";
+            if (L.kind == SSA_LAW_HILL_REPRESS) {
+                o << "        T f = P::div(c[" << j << "], d, 0u);\n";
+            } else {
+                o << "        T g = P::mul(c[" << j << "], qh, 0u);\n"
+                  << "        T f = P::div(g, d, 0u);\n";
+            }
+            o << "        a[" << j << "] = P::add(hill[" << 2 * j << "], f, 0u); }\n";
+        }
+    }
+    return o.str();
+}
+
 // Device description of one network: propensity op sequence with its static
 // rounding slots (main and conversion), and the integer update x += nu_mu.
 std::string gen_model(const Model &md, int idx, uint64_t record_mask)
@@ -194,7 +274,10 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
       << "  __device__ static __forceinline__ void propensities(const i32 (&x)[N], const typename P::T (&c)[M],"
       << " const typename P::T *hill, typename P::T (&a)[M], const PoolT &pool, const CPoolT &cpool) {\n"
       << "    typedef typename P::T T;\n"
-      << "    (void)hill; (void)pool; (void)cpool;\n";
+      << "    (void)hill; (void)pool; (void)cpool;\n"
+      << "    if constexpr (P::NATIVE16) {\n"
+      << gen_propensities_packed(md)
+      << "    } else {\n";
     int slot = 0, cslot = 0;
     for (int j = 0; j < md.M; ++j) {
         const ssa_law &L = md.law[j];
@@ -239,6 +322,7 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
             slot = sl;
         }
     }
+    o << "    }\n";
     // x += nu_mu, mu in [0, M] (mu = M: nothing fires). A species whose net
     // changes fit W-bit signed fields for all M + 1 values of mu reads its
     // change from one packed constant with a single bitfield extract; any other
@@ -369,7 +453,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
       << "  if (w < 4) {\n"
       << "    __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, 0u};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
       << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"

@@ -241,7 +241,7 @@ struct PrecF64 {
     typedef double T;
     typedef double A;
     typedef double Tm;
-    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true, SELECTIVE = false;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = true, SELECTIVE = false, NATIVE16 = false;
     static constexpr i32 EXACT_INT = 0;   // conversions are exact: no count test
     static constexpr int SR_B = 16;
     template <bool EXACT>
@@ -262,7 +262,7 @@ struct PrecF32 {
     typedef float T;
     typedef float A;
     typedef float Tm;
-    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false, SELECTIVE = false;
+    static constexpr bool SR = false, UNI = false, NORM = false, WIDE = false, SELECTIVE = false, NATIVE16 = false;
     static constexpr i32 EXACT_INT = 0;
     static constexpr int SR_B = 16;
     template <bool EXACT>
@@ -353,12 +353,34 @@ struct Prec16 {
         else
             return rnd16<FMT, SR_OPS>((float)(x - i), rb);
     }
-    __device__ static T mul(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(mul32<FMT>(a, b), rb); }
+    // Round to nearest in fp16: the hardware's fp16 product and sum
+    // (v_mul_f16, v_add_f16) are the correctly rounded results, equal to the
+    // binary32 op followed by one rounding (exact product; innocuous double
+    // rounding for the sum, 24 >= 2*11 + 2). Division keeps the binary32
+    // quotient and one rounding (the compiler's fp16 division is not an IEEE
+    // operation).
+    static constexpr bool NATIVE16 = FMT == FMT_FP16 && !SR_OPS;
+    __device__ static T mul(T a, T b, u32 rb)
+    {
+        if constexpr (NATIVE16)
+            return (float)((_Float16)a * (_Float16)b);
+        else
+            return rnd16<FMT, SR_OPS>(mul32<FMT>(a, b), rb);
+    }
     __device__ static T div(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(a / b, rb); }
-    __device__ static T add(T a, T b, u32 rb) { return rnd16<FMT, SR_OPS>(add32<FMT>(a, b), rb); }
+    __device__ static T add(T a, T b, u32 rb)
+    {
+        if constexpr (NATIVE16)
+            return (float)((_Float16)a + (_Float16)b);
+        else
+            return rnd16<FMT, SR_OPS>(add32<FMT>(a, b), rb);
+    }
     __device__ static A acc(A s, T a, u32 rb)
     {
-        return UNIF ? rnd16<FMT, SR_ACC>(add32<FMT>(s, a), rb) : add32<FMT>(s, a);
+        if constexpr (UNIF && FMT == FMT_FP16 && !SR_ACC)
+            return (float)((_Float16)s + (_Float16)a);
+        else
+            return UNIF ? rnd16<FMT, SR_ACC>(add32<FMT>(s, a), rb) : add32<FMT>(s, a);
     }
     __device__ static A arnd(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_OPS>(v, rb) : v; }
     __device__ static A tacc(A v, u32 rb) { return UNIF ? rnd16<FMT, SR_ACC>(v, rb) : v; }
@@ -400,6 +422,15 @@ struct Pool {
     static constexpr int NSTREAM = NSLOT <= F0 ? 1 : 1 + (NSLOT - F0 + F1 - 1) / F1;
     static constexpr int NW = NSLOT <= 0 ? 1 : 3 + 4 * (NSTREAM - 1);
     u32 w[NW];
+    // the third word, whose bit 31 a producer sets on a draw whose ring slot
+    // also holds its conversion fields (no field uses that bit)
+    __device__ __forceinline__ u32 mark() const
+    {
+        if constexpr (NW > 2)
+            return w[2];
+        else
+            return 0u;
+    }
     // slots past the pool belong to ops that do not round stochastically
     __device__ __forceinline__ u32 hw(int s) const
     {
@@ -748,7 +779,6 @@ struct RingFeed {
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
     u32 dw;         // counter word of the draw the lane takes next (event n + 1)
-    u32 cflag;      // the lane has asked its producer for conversion fields
 
     // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
     // made is reset to "nothing made in this epoch" before the epoch is
@@ -764,7 +794,6 @@ struct RingFeed {
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
         lds_st(&ctl->convw[lane], 0u);
-        cflag = 0u;
         lgkm_wait();
         lds_st(&ctl->req_e[lane], eb);
     }
@@ -772,25 +801,22 @@ struct RingFeed {
     // Conversion fields of the current event's draw (event n, counter word
     // dw - 256): from its ring slot where the producer formed them with the
     // draw (the draw came from the ring and carries the mark), formed here
-    // for the lanes that need them otherwise. need: this lane's counts exceed
-    // the exact-integer limit (only then do its fields matter); it also asks
-    // the producer to form them for the rest of the trajectory. The slot is
+    // for the lanes that need them otherwise. need: the lanes whose counts
+    // exceed the exact-integer limit (only then do their fields matter); each
+    // lane's bit goes to the producer as its request word. The slot is
     // intact: the producer may rewrite it only once done passes event n, which
     // read() publishes after this event's loads have completed.
-    template <int NCONV, int B, int OFF>
-    __device__ ConvPool<NCONV, B> conv(u32 mark, bool need, u64 act, u64 n, u32 id, u32 k0, u32 k1)
+    // pre: the slot's conversion words, loaded with the draw (read_conv in the
+    // previous event; meaningful where the draw carries the mark).
+    template <int NCONV, int B>
+    // need: the lanes whose counts exceed the exact-integer limit.
+    __device__ ConvPool<NCONV, B> conv(const ConvPool<NCONV, B> &pre, u32 mark, u64 need, u64 n, u32 id, u32 k0,
+                                       u32 k1)
     {
-        ConvPool<NCONV, B> cp;
-        const u32 *sl = (const u32 *)((const char *)(ring + lane) + ((dw - 256u) & (u32)((D - 1) << 8)));
-#pragma unroll
-        for (int q = 0; q < ConvPool<NCONV, B>::NSTREAM * 4; ++q)
-            cp.w[q] = sl[(OFF + q) * D * 64];
-        if (need && !cflag) {
-            lds_st(&ctl->convw[lane], 1u);
-            cflag = 1u;
-        }
-        const bool have = (mark & 0x80000000u) != 0u;
-        const u64 self = act & lanes(need) & ~lanes(have);
+        ConvPool<NCONV, B> cp = pre;
+        lds_st(&ctl->convw[lane], (u32)(need >> lane) & 1u);
+        const bool have = (i32)mark < 0;   // the mark is bit 31
+        const u64 self = need & ~lanes(have);
         if (__builtin_expect(self != 0, 0)) {
             __asm__ volatile("");
             const ConvPool<NCONV, B> f = make_conv<NCONV, B>(n, id, k0, k1);
@@ -816,6 +842,17 @@ struct RingFeed {
         lgkm_wait();   // the made word, and the previous draw's ring words, are in
         lds_st(&ctl->done[lane], dw);
         DrawIO<P, NSLOT>::template load_pool<D * 64>(slot(), d);
+    }
+
+    // the conversion words of the next draw's slot, loaded with its pool words
+    // (models whose conversions round stochastically): in registers by the
+    // time an event on the conversion path needs them
+    template <int NCONV, int B, int OFF>
+    __device__ void read_conv(ConvPool<NCONV, B> &cp) const
+    {
+#pragma unroll
+        for (int q = 0; q < ConvPool<NCONV, B>::NSTREAM * 4; ++q)
+            cp.w[q] = slot()[(OFF + q) * D * 64];
     }
 
     // its L and u2, loaded once this event's are no longer needed
@@ -971,6 +1008,78 @@ __host__ __device__ constexpr int cmax(int a, int b)
 }
 
 // --------------------------------------------------------------------------
+// Propensity versions. Each computes the same values wherever it runs; a state
+// needs one of them (wave-uniform, over the lanes holding a trajectory):
+//   VER_EXACT    every count exactly representable in the propensity type (or
+//                a binary type), none below a reactant order: no zero guard;
+//   VER_GUARD    counts exact, some count below its order: zero guards;
+//   VER_CONV     some count above the exact-integer limit (its conversion
+//                rounds and draws conversion fields), zero guards;
+//   VER_CONV_NG  the same with every count at or above its orders.
+// The event loop runs one straight-line loop per version and leaves it when
+// the updated state needs another, so a wave that stays in one version (a
+// long trajectory far above the exact-integer limit) takes no branch but the
+// loop's own each event.
+// --------------------------------------------------------------------------
+enum { VER_EXACT = 0, VER_GUARD = 1, VER_CONV = 2, VER_CONV_NG = 3 };
+
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+
+template <class P, class Md>
+struct Versions {
+    static constexpr bool CONV = P::SR && !P::SELECTIVE && Md::NCONV > 0;
+    static constexpr bool GUARD = Md::LO_MAX > 0;
+
+    __device__ static __forceinline__ u32 max_count(const i32 (&x)[Md::N])
+    {
+        u32 mx = (u32)x[0];
+#pragma unroll
+        for (int s = 1; s < Md::N; ++s)
+            mx = (u32)x[s] > mx ? (u32)x[s] : mx;
+        return mx;
+    }
+
+    // counts are never negative; as unsigned, a negative one would only send
+    // the wave to the version that handles every count
+    __device__ static __forceinline__ int of(const i32 (&x)[Md::N], u64 act)
+    {
+        if constexpr (CONV) {
+            if ((act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX))) == 0)
+                return VER_EXACT;
+            if ((act & lanes(max_count(x) > (u32)P::EXACT_INT)) == 0)
+                return VER_GUARD;
+            return (GUARD && (act & lanes(Md::below(x))) != 0) ? VER_CONV : VER_CONV_NG;
+        } else if constexpr (GUARD) {
+            return (act & lanes(Md::below(x))) == 0 ? VER_EXACT : VER_GUARD;
+        } else {
+            return VER_EXACT;
+        }
+    }
+
+    // the state still needs version V (one wave test where it can be decided by one)
+    template <int V>
+    __device__ static __forceinline__ bool still(const i32 (&x)[Md::N], u64 act)
+    {
+        if constexpr (V == VER_EXACT) {
+            if constexpr (CONV)
+                return (act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX))) == 0;
+            else if constexpr (GUARD)
+                return (act & lanes(Md::below(x))) == 0;
+            else
+                return true;
+        } else if constexpr (V == VER_CONV_NG) {
+            return ((act & lanes(max_count(x) > (u32)P::EXACT_INT)) != 0) &&
+                   (!GUARD || (act & lanes(Md::below(x))) == 0);
+        } else {
+            return of(x, act) == V;
+        }
+    }
+};
+
+// --------------------------------------------------------------------------
 // One wave works through one item: lanes claim trajectories from the item's
 // counter, run events, and claim again as they finish (ballot + prefix rank,
 // one atomic per refill), until the counter passes E and every lane is idle.
@@ -983,6 +1092,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
     typedef typename P::A A;
     typedef typename P::Tm Tm;
     typedef Slots<P, Md> S;
+    typedef Versions<P, Md> VS;
     constexpr int N = Md::N, M = Md::M;
     constexpr int NSLOT = S::NSLOT;
     constexpr int SLOT_NORM = S::NORM;
@@ -1007,6 +1117,11 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
     Tm t_next = 0;     // time of snapshot k (infinity past the last row of this launch)
     Tm t_stop = 0;     // an event at t_new fires only if t_new <= t_stop (-infinity: suspend)
     Draw<P, NSLOT> cur = {};
+    // conversion words of cur's ring slot (RingFeed, models whose conversions
+    // round stochastically); used only where cur carries the producer's mark
+    constexpr bool CONV_RING = F::RING && ConvRing<P, Md>::ON;
+    typedef ConvPool<Md::NCONV, P::SR_B> CP;
+    CP conv_cur = {};
     u64 n_claim = 0;   // event index when this launch claimed the trajectory
     u32 rec_cnt = 0;   // recorded firings of this trajectory (Md::REC reactions)
     const u64 n_stop = L.max_events ? L.max_events : ~0ull;
@@ -1114,8 +1229,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
             // taken back-branch lands decides how many instruction-fetch lines an
             // event spans (the same loop measured up to 5% apart between offsets;
             // the padding runs once, before the loop)
-            __asm__ volatile(".p2align 6");
-            do {   // one event step per iteration, until some lane stops
+            // One event step in propensity version V; returns whether the next
+            // event needs the same version.
+            auto step = [&](auto vtag) __attribute__((always_inline)) -> bool {
+                constexpr int V = decltype(vtag)::value;
                 // ---- draws: cur belongs to event n; event n+1's is formed (or
                 // taken from the producer's ring) alongside
                 const u32 id = I.id_base + idx;
@@ -1126,51 +1243,36 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 else
                     nxt = make_draw<P, NSLOT, SLOT_LOG>(n + 1, id, L.seed_lo, L.seed_hi);
                 const Pool<NSLOT, P::SR_B> &pool = cur.pool;
-                // ---- propensities (generated op sequence). Conversions of
-                // counts draw random bits only when they round: when every
-                // count of every lane is exactly representable in the 16-bit
-                // type the exact version runs and no conversion stream is drawn.
-                // A mass-action propensity is zero when a count is below its
-                // order; with every count at or above its species' largest
-                // order no guard can apply, and the version without them runs.
-                // Each version computes the same values where it runs.
+                // ---- propensities (generated op sequence) in version V.
+                // Conversions of counts draw random bits only when they round:
+                // with every count exactly representable in the 16-bit type
+                // no conversion stream is drawn. A mass-action propensity is
+                // zero when a count is below its order; with every count at or
+                // above its species' largest order no guard can apply.
                 T a[M];
-                if constexpr (P::SR && !P::SELECTIVE && Md::NCONV > 0) {
-                    // counts are never negative; as unsigned, a negative one would
-                    // only send the wave to the version that handles every count
-                    if (__builtin_expect(
-                            (act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX))) == 0, 1)) {
-                        Md::template propensities<P, true, false>(x, c, hill, a, pool, NoConv());
-                    } else {
-                        u32 mx = (u32)x[0];
-#pragma unroll
-                        for (int s = 1; s < N; ++s)
-                            mx = (u32)x[s] > mx ? (u32)x[s] : mx;
-                        if ((act & lanes(mx > (u32)P::EXACT_INT)) == 0) {
-                            Md::template propensities<P, true, true>(x, c, hill, a, pool, NoConv());
-                        } else {
-                            // the empty asm keeps this a branch: merged with the exact
-                            // version, the conversion stream would be drawn every event
-                            __asm__ volatile("");
-                            ConvPool<Md::NCONV, P::SR_B> cpool;
-                            if constexpr (F::RING)   // from the producer where it formed them
-                                cpool = feed.template conv<Md::NCONV, P::SR_B, DrawIO<P, NSLOT>::NW>(
-                                    cur.pool.w[2], mx > (u32)P::EXACT_INT, act, n, id, L.seed_lo, L.seed_hi);
-                            else
-                                cpool = make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
-                            Md::template propensities<P, false, true>(x, c, hill, a, pool, cpool);
-                        }
-                    }
-                } else if constexpr (Md::LO_MAX > 0) {
-                    if (__builtin_expect((act & lanes(Md::below(x))) == 0, 1))
-                        Md::template propensities<P, false, false>(x, c, hill, a, pool, NoConv());
-                    else
-                        Md::template propensities<P, false, true>(x, c, hill, a, pool, NoConv());
+                if constexpr (V == VER_EXACT) {
+                    Md::template propensities<P, VS::CONV, false>(x, c, hill, a, pool, NoConv());
+                } else if constexpr (V == VER_GUARD) {
+                    Md::template propensities<P, VS::CONV, true>(x, c, hill, a, pool, NoConv());
                 } else {
-                    Md::template propensities<P, false, false>(x, c, hill, a, pool, NoConv());
+                    // conversion fields: from the producer where it formed them
+                    // (ring feed), else formed here
+                    const u64 need_conv = act & lanes(VS::max_count(x) > (u32)P::EXACT_INT);
+                    CP cpool;
+                    if constexpr (F::RING)
+                        cpool = feed.template conv<Md::NCONV, P::SR_B>(conv_cur, cur.pool.mark(), need_conv, n, id,
+                                                                        L.seed_lo, L.seed_hi);
+                    else
+                        cpool = make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
+                    (void)need_conv;
+                    Md::template propensities<P, false, V == VER_CONV>(x, c, hill, a, pool, cpool);
                 }
-                if constexpr (F::RING)
+                CP conv_nxt;
+                if constexpr (F::RING) {
                     feed.read(nxt);
+                    if constexpr (CONV_RING)
+                        feed.template read_conv<Md::NCONV, P::SR_B, DrawIO<P, NSLOT>::NW>(conv_nxt);
+                }
                 // ---- optional running-max normalisation (uniform 16-bit)
                 T m = (T)1;
                 m_ok = true;
@@ -1263,8 +1365,49 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 if constexpr (F::RING)
                     feed.template finish<P, NSLOT, SLOT_LOG>(nxt, made_w, n, id, act, L.seed_lo, L.seed_hi);
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
+                if constexpr (CONV_RING)
+                    conv_cur = conv_nxt;
                 stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
-            } while (__builtin_expect(stop_lanes == 0, 1));
+                return VS::template still<V>(x, act);
+            };
+            // one straight-line loop per version; its first instruction on a
+            // 64-byte boundary (where the taken back-branch lands decides how
+            // many instruction-fetch lines an event spans; the same loop
+            // measured up to 5% apart between offsets; the padding runs once)
+            int ver = VS::of(x, act);
+            for (;;) {
+                bool stay;
+                if (ver == VER_EXACT) {
+                    __asm__ volatile(".p2align 6");
+                    do {
+                        stay = step(IC<VER_EXACT>());
+                    } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                } else if (VS::GUARD && ver == VER_GUARD) {
+                    if constexpr (VS::GUARD) {
+                        __asm__ volatile(".p2align 6");
+                        do {
+                            stay = step(IC<VER_GUARD>());
+                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                    }
+                } else if (VS::CONV && ver == VER_CONV_NG) {
+                    if constexpr (VS::CONV) {
+                        __asm__ volatile(".p2align 6");
+                        do {
+                            stay = step(IC<VER_CONV_NG>());
+                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                    }
+                } else {
+                    if constexpr (VS::CONV && VS::GUARD) {
+                        __asm__ volatile(".p2align 6");
+                        do {
+                            stay = step(IC<VER_CONV>());
+                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                    }
+                }
+                if (stop_lanes != 0)
+                    break;
+                ver = VS::of(x, act);
+            }
             if (active && (!fire || n == n_stop)) {
                 if (!fire)
                     n -= 1;

@@ -13,8 +13,8 @@ trajectories that cycle the 255 epochs many times, event indices crossing the
 24-bit wrap, and a producer that sees claims late (it then skips ahead).
 
 Conversion fields: a lane whose counts pass the exact-integer limit sets its
-request word; the producer then also forms each draw's conversion fields into
-the slot and marks the draw. In an event that needs them the lane reads the
+request word (in every event that needs them); the producer then also forms
+each draw's conversion fields into the slot and marks the draw. In an event that needs them the lane reads the
 current draw's fields from its slot (before it publishes done) if that draw
 came from the ring with the mark, and forms them itself otherwise; fields it
 reads must be its own draw's.
@@ -74,7 +74,6 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
         yield
         sh.req_id, sh.req_lo, sh.req_hi = uid, n & 0xFFFFFFFF, n >> 32
         sh.convw = 0
-        cflag = False
         yield
         sh.req_e = eb
         yield
@@ -88,10 +87,8 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
             if need_from is not None and ev >= need_from:     # conversion path: fields of draw n
                 fields = sh.conv[(((dw - 256) & M32) >> 8) % D]
                 yield
-                if not cflag:
-                    sh.convw = 1
-                    cflag = True
-                    yield
+                sh.convw = 1                                  # the request word, every such event
+                yield
                 if cur_mark:
                     log["conv_ring"] += 1
                     assert fields == (uid, n), f"stale conversion fields: got {fields}, wanted {(uid, n)}"
