@@ -109,14 +109,17 @@ def timed_runs(ssa, items, W, mode, args, log):
     last = runs[-1]
     status = np.zeros(4, dtype=np.int64)
     item_events = []
+    max_events = 0
     for i in range(len(W.items)):
         st = last.stats(i)
         status += np.bincount(st["status"], minlength=4)[:4]
         item_events.append(float(st["n_events"].sum()))
+        if st["n_events"].size:
+            max_events = max(max_events, int(st["n_events"].max()))
     return {"wall_s": wall, "events": events, "events_per_step": events / args.steps,
             "kernel_ms_avg": float(np.mean(kern_ms)), "info": infos[-1],
             "marg": None if args.no_fidelity else marginals(last, W), "status_counts": status.tolist(),
-            "item_events": item_events}
+            "item_events": item_events, "max_events": max_events}
 
 
 VALU_CLASSES = ["v_add_u32", "v_bitop3_b32", "v_mad_u64_u32", "v_mul_f32", "v_fma_f32", "v_mul_f64", "v_fma_f64",
@@ -333,6 +336,13 @@ def main():
                      "kernel_object": os.path.basename(ve["file"]), "kernel_ms": ms,
                      "valu_slots_per_event": ve["valu_slots"], "valu_insts_per_event": ve["valu_insts"]},
     }
+    # the chain bound: no launch ends before its longest trajectory has fired all
+    # its events one after another; cycles per event of that chain at the nominal clock
+    out["chain"] = {"max_events_per_trajectory": main_res["max_events"],
+                    "cycles_per_event_at_2.4GHz": ms * 1e-3 * 2.4e9 / max(main_res["max_events"], 1),
+                    "fp64_max_events_per_trajectory": ref_res["max_events"],
+                    "fp64_cycles_per_event_at_2.4GHz":
+                        ref_res["kernel_ms_avg"] * 1e-3 * 2.4e9 / max(ref_res["max_events"], 1)}
     if not passed:
         out["value_failing_fidelity"] = rate
     out["fp64"]["kernel_object"] = os.path.basename(ve_ref["file"])

@@ -199,6 +199,11 @@ typedef struct ssa_item {
                                           to wave 0 of workgroup 1, ...), so after a
                                           reordering window the heaviest trajectories share
                                           one wave per workgroup                            */
+#define SSA_PLACE_SOLO_WAVE0 8         /* 512-thread workgroups: event-loop wave 0 runs with its
+                                          SIMD to itself (producers feed the next SIMD's wave,
+                                          event-loop wave 3 forms its own draws, wave 4 does
+                                          not run); with SSA_PLACE_WAVE_MAJOR the heaviest
+                                          trajectories get those SIMDs                      */
 
 typedef struct ssa_run_desc {
     const ssa_item *items;
@@ -224,7 +229,10 @@ typedef struct ssa_run_desc {
 
 /* Start an ensemble run; returns once the work is queued on hip_stream
  * (asynchronous). The first run of a (networks, precision) combination
- * compiles its kernel (hipRTC, cached in memory and on disk).
+ * compiles its kernel for gfx950 (ROCm's offline clang at
+ * $ROCM_PATH/llvm/bin/clang++, run as a child process, or the one named by
+ * SSA_RP_CLANG; hipRTC when there is none or SSA_RP_CLANG is empty), cached
+ * in memory and on disk (SSA_RP_CACHE_DIR, else _kcache beside the library).
  *   out: receives the run; release with ssa_run_destroy.
  * Errors: SSA_E_INVALID (see ssa_run_desc), SSA_E_UNSUPPORTED (precision
  *   combination), SSA_E_COMPILE, SSA_E_NOMEM, SSA_E_DEVICE. */

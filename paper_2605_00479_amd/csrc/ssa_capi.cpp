@@ -3,10 +3,11 @@
 //  * ssa_model_create validates a reaction network and keeps a copy.
 //  * ssa_ensemble_run rounds the rate constants once to the run's precision,
 //    generates the network description for the device template
-//    (ssa_device.hip), compiles it with hipRTC for gfx950 (cached in memory
-//    and on disk), uploads tables and launches the persistent kernel, in one
-//    launch or in snapshot-window chunks (direct launches, or beyond
-//    kGraphMinChunks windows one hipGraph captured and launched per run).
+//    (ssa_device.hip), compiles it for gfx950 with ROCm's offline clang
+//    (hipRTC where there is none; cached in memory and on disk), uploads
+//    tables and launches the persistent kernel, in one launch or in
+//    snapshot-window chunks (direct launches, or beyond kGraphMinChunks
+//    windows one hipGraph captured and launched per run).
 //  * getters copy results out; ssa_run_info_get reports HIP-event timings.
 #include "ssa_rp.h"
 
@@ -14,8 +15,13 @@
 #include <hip/hiprtc.h>
 
 #include <dlfcn.h>
+#include <fcntl.h>
+#include <spawn.h>
 #include <sys/stat.h>
+#include <sys/wait.h>
 #include <unistd.h>
+
+#include <cerrno>
 
 #include <algorithm>
 #include <cmath>
@@ -418,11 +424,14 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
         o << ")";
     o << ";\n"
       << "constexpr int SSA_RING_D = ring_depth(SSA_RING_NW);\n"
-      << "extern \"C\" __global__ void __launch_bounds__(512) ssa_kernel_pc(LaunchArgs L) {\n"
+      << "// 512 threads are two waves per SIMD: at most 256 registers (VGPRs and AGPRs\n"
+      << "// together) per wave, which the waves-per-EU bound makes the compiler keep\n"
+      << "extern \"C\" __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))\n"
+      << "ssa_kernel_pc(LaunchArgs L) {\n"
       << "  const u32 w = threadIdx.x >> 6, lane = lane_id();\n"
       << "  // event-loop wave c (= w for w < 4) is fed by the producer wave on its own\n"
       << "  // SIMD (w = c + 4) or, with PLACE_NEIGHBOUR, on the next one (w = 4 + (c + 1) % 4)\n"
-      << "  const u32 c = w < 4u ? w : ((w + ((L.place & PLACE_NEIGHBOUR) ? 3u : 0u)) & 3u);\n"
+      << "  const u32 c = w < 4u ? w : ((w + ((L.place & (PLACE_NEIGHBOUR | PLACE_SOLO0)) ? 3u : 0u)) & 3u);\n"
       << "  if constexpr (SSA_RING_D == 0) {\n"
       << "    SelfFeed feed;\n"
       << "    const u32 slot_rank = w * gridDim.x + blockIdx.x, n_slots = gridDim.x * 8u;\n"
@@ -451,7 +460,22 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  __syncthreads();\n"
       << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
-      << "  if (w < 4) {\n"
+      << "  const bool solo0 = (L.place & PLACE_SOLO0) != 0u;\n"
+      << "  if (w < 4 && solo0 && c == 3u) {\n"
+      << "    // PLACE_SOLO0: event-loop wave 3 forms its own draws\n"
+      << "    __builtin_amdgcn_s_setprio(3);\n"
+      << "    SelfFeed feed;\n"
+      << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
+      << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
+      << "      switch (it) {\n";
+    for (size_t i = 0; i < models.size(); ++i)
+        o << "      case " << i << ": run_item<PrecRun, Md" << i << ", " << (per_lane_rates[i] ? "true" : "false")
+          << ">(L, L.item[" << i << "], feed, slot_rank, n_slots); break;\n";
+    o << "      default: break;\n"
+      << "      }\n"
+      << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
+      << "    }\n"
+      << "  } else if (w < 4) {\n"
       << "    __builtin_amdgcn_s_setprio(3);\n"
       << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
       << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
@@ -467,7 +491,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
       << "    lds_st(&ctl[c].item, ~0u);\n"
-      << "  } else {\n"
+      << "  } else if (!(solo0 && w == 4u)) {   // PLACE_SOLO0: wave 4 leaves SIMD 0 to wave 0\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
@@ -492,8 +516,13 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
 // hide latency rather than save registers for occupancy: AMDGPU's max-ILP
 // scheduling strategy (measured on the Schloegl benchmark: FP64 5% and
 // MIX_F16_SR 1% faster per step than the default strategy).
+// Spills of a very large network go to scratch, not to AGPRs: some compilers
+// (the hipRTC that the PyTorch wheel bundles) add AGPRs beyond the 256
+// registers per wave that two waves per SIMD (512-thread workgroups) allow,
+// and such a kernel cannot be dispatched at that size.
 const char *const kJitOptions[] = {"-O3", "-std=c++17", "-ffp-contract=off", "-Xclang", "-target-feature",
-                                   "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-sched-strategy=max-ilp"};
+                                   "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-sched-strategy=max-ilp",
+                                   "-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"};
 
 uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull)
 {
@@ -522,27 +551,93 @@ struct CompiledKernel {
     std::vector<char> code;
 };
 
-int compile_source(const std::string &src, const std::string &arch, std::vector<char> &code,
-                   std::string *path_out = nullptr)
+// ROCm's offline clang, run as a child process, compiles the kernels: the
+// in-process hipRTC resolves to whichever comgr the host process loaded first
+// (inside PyTorch, the one its wheel bundles), and that compiler gives the
+// largest networks' 512-thread kernels more registers than two waves per SIMD
+// can hold. SSA_RP_CLANG names another clang; set to an empty string it selects
+// hipRTC. Without an offline clang, hipRTC compiles.
+std::string offline_compiler()
 {
-    const std::string key = arch + "\n" + src;
-    uint64_t h = fnv1a(key);
-    for (const char *opt : kJitOptions)
-        h = fnv1a(opt, h);
-    char name[64];
-    std::snprintf(name, sizeof name, "%016llx.co", (unsigned long long)h);
-    const std::string dir = cache_dir();
-    const std::string path = dir + "/" + name;
-    if (path_out)
-        *path_out = path;
+    if (const char *e = std::getenv("SSA_RP_CLANG"))
+        return e;
+    const char *rp = std::getenv("ROCM_PATH");
+    const std::string p = std::string(rp && *rp ? rp : "/opt/rocm") + "/llvm/bin/clang++";
+    return ::access(p.c_str(), X_OK) == 0 ? p : std::string();
+}
+
+bool read_file(const std::string &path, std::vector<char> &out)
+{
+    std::ifstream in(path, std::ios::binary);
+    if (!in)
+        return false;
+    out.assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
+    return true;
+}
+
+// compile src into a gfx950 code object with the clang at cc (child process;
+// its messages go to a log file that an error reports)
+int compile_offline(const std::string &cc, const std::string &src, const std::string &arch,
+                    std::vector<char> &code)
+{
+    const char *td = std::getenv("TMPDIR");
+    char tmpl[512];
+    std::snprintf(tmpl, sizeof tmpl, "%s/ssa_rp_jit_XXXXXX", td && *td ? td : "/tmp");
+    if (!::mkdtemp(tmpl))
+        return fail(SSA_E_COMPILE, std::string("cannot create a directory for the kernel build: ") + tmpl);
+    const std::string dir = tmpl, in = dir + "/k.hip", out = dir + "/k.co", log = dir + "/k.log";
+    auto cleanup = [&] {
+        std::remove(in.c_str());
+        std::remove(out.c_str());
+        std::remove(log.c_str());
+        ::rmdir(dir.c_str());
+    };
     {
-        std::ifstream in(path, std::ios::binary);
-        if (in) {
-            code.assign(std::istreambuf_iterator<char>(in), std::istreambuf_iterator<char>());
-            if (!code.empty())
-                return SSA_OK;
+        std::ofstream f(in, std::ios::binary);
+        f.write(src.data(), (std::streamsize)src.size());
+        if (!f) {
+            cleanup();
+            return fail(SSA_E_COMPILE, "cannot write the kernel source to " + in);
         }
     }
+    std::vector<std::string> args = {cc, "-x", "hip", "--offload-arch=" + arch, "--offload-device-only",
+                                     "--no-gpu-bundle-output", "-include", "hip/hip_runtime.h"};
+    for (const char *opt : kJitOptions)
+        args.push_back(opt);
+    args.insert(args.end(), {"-o", out, in});
+    std::vector<char *> argv;
+    for (auto &a : args)
+        argv.push_back(&a[0]);
+    argv.push_back(nullptr);
+    posix_spawn_file_actions_t fa;
+    posix_spawn_file_actions_init(&fa);
+    posix_spawn_file_actions_addopen(&fa, 0, "/dev/null", O_RDONLY, 0);
+    posix_spawn_file_actions_addopen(&fa, 1, log.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+    posix_spawn_file_actions_adddup2(&fa, 1, 2);
+    pid_t pid = 0;
+    const int se = posix_spawn(&pid, cc.c_str(), &fa, nullptr, argv.data(), environ);
+    posix_spawn_file_actions_destroy(&fa);
+    if (se != 0) {
+        cleanup();
+        return fail(SSA_E_COMPILE, "cannot start " + cc + ": " + std::strerror(se));
+    }
+    int status = 0;
+    while (::waitpid(pid, &status, 0) < 0 && errno == EINTR) {
+    }
+    const bool ok = WIFEXITED(status) && WEXITSTATUS(status) == 0 && read_file(out, code) && !code.empty();
+    if (!ok) {
+        std::vector<char> msg;
+        read_file(log, msg);
+        cleanup();
+        return fail(SSA_E_COMPILE, "kernel compilation (" + cc + ") failed: " +
+                                       std::string(msg.begin(), msg.end()).substr(0, 4000));
+    }
+    cleanup();
+    return SSA_OK;
+}
+
+int compile_hiprtc(const std::string &src, const std::string &arch, std::vector<char> &code)
+{
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "ssa_jit.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return fail(SSA_E_COMPILE, "hiprtcCreateProgram failed");
@@ -566,6 +661,30 @@ int compile_source(const std::string &src, const std::string &arch, std::vector<
     code.resize(cs);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
+    return SSA_OK;
+}
+
+// the code object for src: from the disk cache (keyed by source, target,
+// options and compiler) or freshly compiled and cached
+int compile_source(const std::string &src, const std::string &arch, std::vector<char> &code,
+                   std::string *path_out = nullptr)
+{
+    const std::string cc = offline_compiler();
+    uint64_t h = fnv1a(arch + "\n" + src);
+    for (const char *opt : kJitOptions)
+        h = fnv1a(opt, h);
+    h = fnv1a(cc.empty() ? std::string("hiprtc") : "clang:" + cc, h);
+    char name[64];
+    std::snprintf(name, sizeof name, "%016llx.co", (unsigned long long)h);
+    const std::string dir = cache_dir();
+    const std::string path = dir + "/" + name;
+    if (path_out)
+        *path_out = path;
+    if (read_file(path, code) && !code.empty())
+        return SSA_OK;
+    const int rc = cc.empty() ? compile_hiprtc(src, arch, code) : compile_offline(cc, src, arch, code);
+    if (rc != SSA_OK)
+        return rc;
     // best-effort disk cache (write to a temporary name, then rename)
     ::mkdir(dir.c_str(), 0755);
     std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
@@ -815,7 +934,7 @@ int validate_desc(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "first_window must be >= 0");
     if (d->placement != 0 && (!(d->placement & SSA_PLACE_EXPLICIT) ||
                               (d->placement & ~(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER |
-                                                SSA_PLACE_WAVE_MAJOR)) != 0))
+                                                SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0)) != 0))
         return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
@@ -1293,8 +1412,12 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, r->block == 512 ? ld.kernel_pc : ld.kernel,
                                                               r->block, r->block == 512 ? ld.pc_lds_pad : 0u));
+    // a workgroup that cannot be resident at all (registers or LDS beyond a
+    // CU's) would fail at dispatch: refuse it here
     if (per_cu < 1)
-        per_cu = 1;
+        return fail(SSA_E_UNSUPPORTED, "the kernel for these networks needs more registers or LDS than one " +
+                                           std::to_string(r->block) + "-thread workgroup per CU allows; use a smaller "
+                                           "block_size (or 0)");
     // lanes running the event loop per workgroup (half of a 512-thread one)
     const int loop_lanes = r->block == 512 ? 256 : r->block;
     int64_t need = (total + loop_lanes - 1) / loop_lanes;
@@ -1306,10 +1429,11 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     // placement bits: explicit (placement = SSA_PLACE_EXPLICIT | flags), else
     // the autotuned choice where the tuned block size is the one launched
     if (d->placement != 0)
-        r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR);
+        r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0);
     else if (have_tuned && tuned.block == r->block)
         r->place = tuned.place;
-    r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0);
+    r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0) |
+               (r->place & SSA_PLACE_SOLO_WAVE0 ? 4 : 0);
 
     r->n_launch = n_chunks;
     if (r->noalloc) {   // direct launches, no events
@@ -1631,7 +1755,7 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     info->first_window = run->n_launch > 1 ? run->first_window : 0;
     info->graph = run->graph ? 1 : 0;
     info->placement = SSA_PLACE_EXPLICIT | (run->place & 1 ? SSA_PLACE_NEIGHBOUR_PRODUCER : 0) |
-                      (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0);
+                      (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0) | (run->place & 4 ? SSA_PLACE_SOLO_WAVE0 : 0);
     return SSA_OK;
 }
 
@@ -1716,6 +1840,7 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
             if (desc->n_items == 1) {
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_WAVE_MAJOR);
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR);
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_SOLO_WAVE0 | SSA_PLACE_WAVE_MAJOR);
             }
             for (int pl : places)
                 for (const ChunkOpt &ch : chunk_opts)

@@ -573,7 +573,11 @@ struct LaunchArgs {
 //     the claim order (heaviest first after a reordering window), so the
 //     heaviest trajectories sit on wave 0 of every workgroup; the work
 //     counter starts past the static claims.
-enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u };
+//   PLACE_SOLO0: wave 0's SIMD holds no other wave: the producers feed the
+//     event-loop waves of the next SIMD (as PLACE_NEIGHBOUR), event-loop wave
+//     3 forms its own draws and wave 4 does not run. With PLACE_WAVE_MAJOR the
+//     heaviest trajectories then run with a SIMD to themselves from the start.
+enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u, PLACE_SOLO0 = 4u };
 
 enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
 
@@ -862,26 +866,29 @@ struct RingFeed {
         DrawIO<P, NSLOT>::template load_tail<D * 64>(slot(), d);
     }
 
-    // where the ring did not hold the next draw of this trajectory, form it
-    // here; then step to the draw after it. With x = made - (dw + 256), the
-    // draw is made (want < made <= want + D, epochs equal) exactly when x
-    // rotated right by 8 is below D: equal epochs leave a zero low byte and the
-    // index difference minus one above it; any other epoch puts a nonzero byte
-    // on top after the rotation
-    template <class P, int NSLOT, int SLOT_LOG>
-    __device__ void finish(Draw<P, NSLOT> &d, u32 mw, u64 want, u32 id, u64 act, u32 k0, u32 k1)
+    // lanes whose next draw the ring does not hold (the event loop forms it
+    // itself). With x = made - (dw + 256), the draw is made (want < made <=
+    // want + D, epochs equal) exactly when x rotated right by 8 is below D:
+    // equal epochs leave a zero low byte and the index difference minus one
+    // above it; any other epoch puts a nonzero byte on top after the rotation
+    __device__ u64 miss_lanes(u32 mw, u64 act) const
     {
         const u32 next = dw + 256u;
         const bool hit = __builtin_amdgcn_alignbit(mw - next, mw - next, 8) < (u32)D;
-        const u64 miss = act & ~lanes(hit);
-        if (__builtin_expect(miss != 0, 0)) {
-            __asm__ volatile("");
-            const Draw<P, NSLOT> s = make_draw<P, NSLOT, SLOT_LOG>(want, id, k0, k1);
-            if ((miss >> lane) & 1u)
-                d = s;
-        }
-        dw = next;
+        return act & ~lanes(hit);
     }
+
+    // form draw `want` for the lanes in miss (the ring did not hold it)
+    template <class P, int NSLOT, int SLOT_LOG>
+    __device__ void self_draw(Draw<P, NSLOT> &d, u64 miss, u64 want, u32 id, u32 k0, u32 k1) const
+    {
+        const Draw<P, NSLOT> s = make_draw<P, NSLOT, SLOT_LOG>(want, id, k0, k1);
+        if ((miss >> lane) & 1u)
+            d = s;
+    }
+
+    // step to the draw after the next one
+    __device__ void advance() { dw += 256u; }
 };
 
 // Producer wave of one item: for each lane, the draws of its consumer lane's
@@ -1310,22 +1317,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 } else {
                     t_new = t + P::tau_div(cur.L, a0);
                 }
-                // ---- snapshots strictly before t_new hold the current state (rare;
-                // the wave-uniform test lets the compiler place the stores out of line)
                 const u64 ok_lanes = act & lanes(a_ok);
-                const bool snap_due = active && a_ok && t_next < t_new;
-                if (__builtin_expect((ok_lanes & lanes(t_next < t_new)) != 0, 0) && snap_due) {
-                    do {
-#pragma unroll
-                        for (int s = 0; s < N; ++s)
-                            I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
-                        ++k;
-                        t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
-                    } while (t_next < t_new);
-                    t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
-                }
-                fire = active && a_ok && t_new <= t_stop;
-                const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
                 // ---- selection: mu = number of prefix sums at or below the target
                 A target;
                 if constexpr (P::UNI)   // binary32 product, then one rounding to the 16-bit type
@@ -1338,16 +1330,39 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
 #pragma unroll
                 for (int j = 0; j < M; ++j)
                     mu += (S[j] <= target) ? 1 : 0;
-                if (__builtin_expect((fire_lanes & lanes(mu == M)) != 0, 0) && fire && mu == M) {
-                    // target at or above the total (rare): the last reaction with a positive propensity.
-                    // The empty asm keeps this a branch: speculated, it would cost 2M ops every event.
+                // ---- rare work behind one wave-uniform test (out of line): snapshots
+                // strictly before t_new hold the current state; a target at or above
+                // the total selects the last reaction with a positive propensity; a
+                // next draw the producer has not made is formed here
+                u64 miss = 0;
+                if constexpr (F::RING)
+                    miss = feed.miss_lanes(made_w, act);
+                if (__builtin_expect(((ok_lanes & (lanes(t_next < t_new) | lanes(mu == M))) | miss) != 0, 0)) {
                     __asm__ volatile("");
-                    int last_pos = 0;
+                    if (active && a_ok && t_next < t_new) {
+                        do {
 #pragma unroll
-                    for (int j = 0; j < M; ++j)
-                        last_pos = (a[j] > (T)0) ? j : last_pos;
-                    mu = last_pos;
+                            for (int s = 0; s < N; ++s)
+                                I.snap[((u64)(k - L.k_lo) * N + s) * I.E + idx] = x[s];
+                            ++k;
+                            t_next = k < L.k_hi ? snap_time<P>(L, k) : (Tm)SSA_INF_F;
+                        } while (t_next < t_new);
+                        t_stop = (!L.last && k >= L.k_hi) ? (Tm)(-SSA_INF_F) : t_end;
+                    }
+                    if (active && a_ok && t_new <= t_stop && mu == M) {
+                        int last_pos = 0;
+#pragma unroll
+                        for (int j = 0; j < M; ++j)
+                            last_pos = (a[j] > (T)0) ? j : last_pos;
+                        mu = last_pos;
+                    }
+                    if constexpr (F::RING) {
+                        if (miss != 0)
+                            feed.template self_draw<P, NSLOT, SLOT_LOG>(nxt, miss, n + 1, id, L.seed_lo, L.seed_hi);
+                    }
                 }
+                fire = active && a_ok && t_new <= t_stop;
+                const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
                 // ---- integer update (mu = M: nothing fires)
                 Md::update(x, fire ? mu : M);
                 t = fire ? t_new : t;
@@ -1363,7 +1378,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                     }
                 }
                 if constexpr (F::RING)
-                    feed.template finish<P, NSLOT, SLOT_LOG>(nxt, made_w, n, id, act, L.seed_lo, L.seed_hi);
+                    feed.advance();
                 cur = nxt;   // a lane that stops here draws afresh when it claims again
                 if constexpr (CONV_RING)
                     conv_cur = conv_nxt;

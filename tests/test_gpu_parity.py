@@ -517,3 +517,36 @@ def test_producer_waves_event_record(gpu, orc):
     spec = wl.telegraph(0.05, 0.05, 20.0, 1.0)
     x0 = np.array([1, 0, 0], np.int32)
     run_records(gpu, orc, spec, x0, 300, 200.0, wl.snapshot_grid(200.0, 11), "MIX_F16_SR", 0b11, 12, seed=4, **PC)
+
+
+# ---------------------------------------------------------------------------
+# Placements of the 512-thread launch (producer on the event-loop wave's own
+# SIMD or the next one, wave-major first claims, wave 0 alone on its SIMD):
+# only where work runs changes, so results are the oracle's in every one.
+# ---------------------------------------------------------------------------
+PLACEMENTS = [3, 5, 7, 9, 13]
+
+
+@pytest.mark.parametrize("placement", PLACEMENTS)
+@pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR"])
+def test_placements_schlogl(gpu, orc, mode, placement):
+    W = wl.config_schlogl()
+    it = W.items[0]
+    run, _, _ = run_both(gpu, orc, it.model, it.x0, 1500, W.t_end, W.snap_t, mode, seed=W.seed,
+                         max_events=W.max_events, block_size=512, grid_size=2, n_chunks=2, first_window=10,
+                         placement=placement)
+    assert run.info()["placement"] == placement
+
+
+@pytest.mark.parametrize("placement", [1, 7, 13])
+def test_placements_dimer_sets_with_conversion_fields(gpu, orc, placement):
+    """Per-lane parameter sets whose counts pass the fp16 exact-integer limit
+    (2048): the producers form the conversion fields for those lanes, under
+    every placement."""
+    rates = np.array([[400.0, 0.1, 0.001, 0.5], [50.0, 0.1, 0.001, 0.5], [900.0, 0.3, 0.0005, 0.5]], np.float64)
+    m = wl.dimer_open()
+    run, snap, _ = run_both(gpu, orc, m, np.array([3000, 8000], np.int32), 3 * 100, 1.5,
+                            wl.snapshot_grid(1.5, 4), "MIX_F16_SR", seed=31, set_rate=rates, traj_per_set=100,
+                            max_events=3_000_000, block_size=512, grid_size=1, n_chunks=2, first_window=1,
+                            placement=placement)
+    assert snap[:, 0, :].max() > 2048
