@@ -204,6 +204,12 @@ typedef struct ssa_item {
                                           event-loop wave 3 forms its own draws, wave 4 does
                                           not run); with SSA_PLACE_WAVE_MAJOR the heaviest
                                           trajectories get those SIMDs                      */
+#define SSA_PLACE_FEED_WAVE0 16        /* 512-thread workgroups: the producer wave that feeds
+                                          event-loop wave 0 issues ahead of event-loop waves
+                                          1-3 (wave priorities), so wave 0 keeps its draws
+                                          while the chip is busy                            */
+#define SSA_PLACE_PRODUCER_FIRST 32    /* 512-thread workgroups: producer waves issue ahead of
+                                          event-loop waves (a producer stops at a full ring) */
 
 typedef struct ssa_run_desc {
     const ssa_item *items;

@@ -428,7 +428,9 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "// together) per wave, which the waves-per-EU bound makes the compiler keep\n"
       << "extern \"C\" __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))\n"
       << "ssa_kernel_pc(LaunchArgs L) {\n"
-      << "  const u32 w = threadIdx.x >> 6, lane = lane_id();\n"
+      << "  // wave index made wave-uniform: role branches are scalar branches, so the\n"
+      << "  // SALU work of one role (priorities, sleeps) never runs in another role's wave\n"
+      << "  const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();\n"
       << "  // event-loop wave c (= w for w < 4) is fed by the producer wave on its own\n"
       << "  // SIMD (w = c + 4) or, with PLACE_NEIGHBOUR, on the next one (w = 4 + (c + 1) % 4)\n"
       << "  const u32 c = w < 4u ? w : ((w + ((L.place & (PLACE_NEIGHBOUR | PLACE_SOLO0)) ? 3u : 0u)) & 3u);\n"
@@ -461,9 +463,15 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
       << "  const bool solo0 = (L.place & PLACE_SOLO0) != 0u;\n"
+      << "  // wave priorities: event-loop waves 3, producers 0; PLACE_PRODUCER_FIRST:\n"
+      << "  // producers 3, event-loop waves 2; PLACE_FEED0: wave 0 and its producer 3,\n"
+      << "  // event-loop waves 1-3 2, the other producers 0\n"
+      << "  const bool pfirst = (L.place & PLACE_PRODUCER_FIRST) != 0u;\n"
+      << "  const bool ev_low = pfirst || ((L.place & PLACE_FEED0) != 0u && c != 0u);\n"
+      << "  const bool pr_high = pfirst || ((L.place & PLACE_FEED0) != 0u && c == 0u);\n"
       << "  if (w < 4 && solo0 && c == 3u) {\n"
       << "    // PLACE_SOLO0: event-loop wave 3 forms its own draws\n"
-      << "    __builtin_amdgcn_s_setprio(3);\n"
+      << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    SelfFeed feed;\n"
       << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
@@ -476,7 +484,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
       << "  } else if (w < 4) {\n"
-      << "    __builtin_amdgcn_s_setprio(3);\n"
+      << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
       << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
@@ -492,6 +500,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "    }\n"
       << "    lds_st(&ctl[c].item, ~0u);\n"
       << "  } else if (!(solo0 && w == 4u)) {   // PLACE_SOLO0: wave 4 leaves SIMD 0 to wave 0\n"
+      << "    if (pr_high) __builtin_amdgcn_s_setprio(3);\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
@@ -934,7 +943,8 @@ int validate_desc(const ssa_run_desc *d)
         return fail(SSA_E_INVALID, "first_window must be >= 0");
     if (d->placement != 0 && (!(d->placement & SSA_PLACE_EXPLICIT) ||
                               (d->placement & ~(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER |
-                                                SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0)) != 0))
+                                                SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
+                                                SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST)) != 0))
         return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
@@ -1429,11 +1439,13 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     // placement bits: explicit (placement = SSA_PLACE_EXPLICIT | flags), else
     // the autotuned choice where the tuned block size is the one launched
     if (d->placement != 0)
-        r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0);
+        r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
+                                   SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST);
     else if (have_tuned && tuned.block == r->block)
         r->place = tuned.place;
     r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0) |
-               (r->place & SSA_PLACE_SOLO_WAVE0 ? 4 : 0);
+               (r->place & SSA_PLACE_SOLO_WAVE0 ? 4 : 0) | (r->place & SSA_PLACE_FEED_WAVE0 ? 8 : 0) |
+               (r->place & SSA_PLACE_PRODUCER_FIRST ? 16 : 0);
 
     r->n_launch = n_chunks;
     if (r->noalloc) {   // direct launches, no events
@@ -1755,7 +1767,8 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     info->first_window = run->n_launch > 1 ? run->first_window : 0;
     info->graph = run->graph ? 1 : 0;
     info->placement = SSA_PLACE_EXPLICIT | (run->place & 1 ? SSA_PLACE_NEIGHBOUR_PRODUCER : 0) |
-                      (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0) | (run->place & 4 ? SSA_PLACE_SOLO_WAVE0 : 0);
+                      (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0) | (run->place & 4 ? SSA_PLACE_SOLO_WAVE0 : 0) |
+                      (run->place & 8 ? SSA_PLACE_FEED_WAVE0 : 0) | (run->place & 16 ? SSA_PLACE_PRODUCER_FIRST : 0);
     return SSA_OK;
 }
 
@@ -1835,12 +1848,18 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
             const int64_t need = std::max<int64_t>(1, (total + 255) / 256);
             const int64_t g = std::min<int64_t>(need, cus);
             // producers on their own or the next SIMD; claims as they come, or
-            // the first ones wave-major (one launch per item only)
+            // the first ones wave-major (one launch per item only), with wave
+            // priorities that favour wave 0's draws
             std::vector<int> places = {SSA_PLACE_EXPLICIT, SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER};
             if (desc->n_items == 1) {
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_WAVE_MAJOR);
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR);
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_SOLO_WAVE0 | SSA_PLACE_WAVE_MAJOR);
+                // the heaviest trajectories alone on a SIMD, fed ahead of the rest
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_SOLO_WAVE0 | SSA_PLACE_WAVE_MAJOR |
+                                 SSA_PLACE_FEED_WAVE0);
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_SOLO_WAVE0 | SSA_PLACE_WAVE_MAJOR |
+                                 SSA_PLACE_PRODUCER_FIRST);
             }
             for (int pl : places)
                 for (const ChunkOpt &ch : chunk_opts)

@@ -577,7 +577,12 @@ struct LaunchArgs {
 //     event-loop waves of the next SIMD (as PLACE_NEIGHBOUR), event-loop wave
 //     3 forms its own draws and wave 4 does not run. With PLACE_WAVE_MAJOR the
 //     heaviest trajectories then run with a SIMD to themselves from the start.
-enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u, PLACE_SOLO0 = 4u };
+//   PLACE_FEED0: the producer feeding event-loop wave 0 runs at wave 0's
+//     priority and event-loop waves 1-3 one below it, so that on a busy chip
+//     wave 0 (with PLACE_WAVE_MAJOR, the heaviest trajectories) keeps its draws
+//   PLACE_PRODUCER_FIRST: producer waves issue ahead of event-loop waves (a
+//     producer stops at a full ring, so it takes only what its consumer uses)
+enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u, PLACE_SOLO0 = 4u, PLACE_FEED0 = 8u, PLACE_PRODUCER_FIRST = 16u };
 
 enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
 
@@ -772,6 +777,7 @@ __device__ __forceinline__ void lds_st(u32 *p, u32 v)
 struct SelfFeed {
     static constexpr bool RING = false;
     __device__ void claim(u32, u64) {}
+    __device__ void request_conv(u32) const {}
 };
 
 template <int D, int NWMAX>
@@ -802,29 +808,32 @@ struct RingFeed {
         lds_st(&ctl->req_e[lane], eb);
     }
 
+    // The request word: while the wave runs a version whose conversions
+    // round, each of its lanes asks the producer for every draw's conversion
+    // fields (set when the wave enters a version loop; a claim clears it).
+    // The producer forms them for the whole wave once any lane asks.
+    __device__ void request_conv(u32 on) const { lds_st(&ctl->convw[lane], on); }
+
     // Conversion fields of the current event's draw (event n, counter word
     // dw - 256): from its ring slot where the producer formed them with the
     // draw (the draw came from the ring and carries the mark), formed here
-    // for the lanes that need them otherwise. need: the lanes whose counts
-    // exceed the exact-integer limit (only then do their fields matter); each
-    // lane's bit goes to the producer as its request word. The slot is
-    // intact: the producer may rewrite it only once done passes event n, which
-    // read() publishes after this event's loads have completed.
+    // for the active lanes whose draw lacks the mark (a draw made before the
+    // request, or formed by the event loop); a lane whose counts are all
+    // exact ignores its fields. The slot is intact: the producer may rewrite
+    // it only once done passes event n, which read() publishes after this
+    // event's loads have completed.
     // pre: the slot's conversion words, loaded with the draw (read_conv in the
     // previous event; meaningful where the draw carries the mark).
     template <int NCONV, int B>
-    // need: the lanes whose counts exceed the exact-integer limit.
-    __device__ ConvPool<NCONV, B> conv(const ConvPool<NCONV, B> &pre, u32 mark, u64 need, u64 n, u32 id, u32 k0,
-                                       u32 k1)
+    __device__ ConvPool<NCONV, B> conv(const ConvPool<NCONV, B> &pre, u32 mark, u64 act, u64 n, u32 id, u32 k0,
+                                       u32 k1) const
     {
         ConvPool<NCONV, B> cp = pre;
-        lds_st(&ctl->convw[lane], (u32)(need >> lane) & 1u);
-        const bool have = (i32)mark < 0;   // the mark is bit 31
-        const u64 self = need & ~lanes(have);
+        const u64 self = act & ~lanes((i32)mark < 0);   // the mark is bit 31
         if (__builtin_expect(self != 0, 0)) {
             __asm__ volatile("");
             const ConvPool<NCONV, B> f = make_conv<NCONV, B>(n, id, k0, k1);
-            if (!have)
+            if ((self >> lane) & 1u)
                 cp = f;
         }
         return cp;
@@ -1264,14 +1273,12 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 } else {
                     // conversion fields: from the producer where it formed them
                     // (ring feed), else formed here
-                    const u64 need_conv = act & lanes(VS::max_count(x) > (u32)P::EXACT_INT);
                     CP cpool;
                     if constexpr (F::RING)
-                        cpool = feed.template conv<Md::NCONV, P::SR_B>(conv_cur, cur.pool.mark(), need_conv, n, id,
+                        cpool = feed.template conv<Md::NCONV, P::SR_B>(conv_cur, cur.pool.mark(), act, n, id,
                                                                         L.seed_lo, L.seed_hi);
                     else
                         cpool = make_conv<Md::NCONV, P::SR_B>(n, id, L.seed_lo, L.seed_hi);
-                    (void)need_conv;
                     Md::template propensities<P, false, V == VER_CONV>(x, c, hill, a, pool, cpool);
                 }
                 CP conv_nxt;
@@ -1392,6 +1399,8 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
             int ver = VS::of(x, act);
             for (;;) {
                 bool stay;
+                if constexpr (CONV_RING)
+                    feed.request_conv(ver >= VER_CONV ? 1u : 0u);
                 if (ver == VER_EXACT) {
                     __asm__ volatile(".p2align 6");
                     do {

@@ -12,12 +12,13 @@ its current trajectory and event. Runs cover slow and fast producers, short
 trajectories that cycle the 255 epochs many times, event indices crossing the
 24-bit wrap, and a producer that sees claims late (it then skips ahead).
 
-Conversion fields: a lane whose counts pass the exact-integer limit sets its
-request word (in every event that needs them); the producer then also forms
-each draw's conversion fields into the slot and marks the draw. In an event that needs them the lane reads the
-current draw's fields from its slot (before it publishes done) if that draw
-came from the ring with the mark, and forms them itself otherwise; fields it
-reads must be its own draw's.
+Conversion fields: when a lane's counts pass the exact-integer limit its wave
+enters a conversion version and sets the request word (once, at that step; a
+claim clears it); the producer then also forms each draw's conversion fields
+into the slot and marks the draw. In an event that needs them the lane reads
+the current draw's fields from its slot (before it publishes done) if that
+draw came from the ring with the mark, and forms them itself otherwise; fields
+it reads must be its own draw's.
 
 This checks the protocol as designed; the GPU tests check the kernel's results.
 """
@@ -84,10 +85,11 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
             want = n + 1
             mw = sh.made                                      # top of the event
             yield
+            if need_from is not None and ev == need_from:     # entering a conversion version
+                sh.convw = 1                                  # the request word, once
+                yield
             if need_from is not None and ev >= need_from:     # conversion path: fields of draw n
                 fields = sh.conv[(((dw - 256) & M32) >> 8) % D]
-                yield
-                sh.convw = 1                                  # the request word, every such event
                 yield
                 if cur_mark:
                     log["conv_ring"] += 1
