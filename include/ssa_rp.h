@@ -210,6 +210,11 @@ typedef struct ssa_item {
                                           while the chip is busy                            */
 #define SSA_PLACE_PRODUCER_FIRST 32    /* 512-thread workgroups: producer waves issue ahead of
                                           event-loop waves (a producer stops at a full ring) */
+#define SSA_PLACE_DEDICATED_FEED0 64   /* 512-thread workgroups: three event-loop waves; wave 0
+                                          alone on its SIMD and its producer alone on the
+                                          next, the other two fed from their own SIMDs (with
+                                          SSA_PLACE_WAVE_MAJOR: the heaviest trajectories on
+                                          wave 0, never short of draws)                    */
 
 typedef struct ssa_run_desc {
     const ssa_item *items;

@@ -432,8 +432,13 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  // SALU work of one role (priorities, sleeps) never runs in another role's wave\n"
       << "  const u32 w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();\n"
       << "  // event-loop wave c (= w for w < 4) is fed by the producer wave on its own\n"
-      << "  // SIMD (w = c + 4) or, with PLACE_NEIGHBOUR, on the next one (w = 4 + (c + 1) % 4)\n"
-      << "  const u32 c = w < 4u ? w : ((w + ((L.place & (PLACE_NEIGHBOUR | PLACE_SOLO0)) ? 3u : 0u)) & 3u);\n"
+      << "  // SIMD (w = c + 4) or, with PLACE_NEIGHBOUR, on the next one (w = 4 + (c + 1) % 4).\n"
+      << "  // PLACE_DEDICATED: event-loop waves 0, 2, 3; wave 0 alone on SIMD 0 and its\n"
+      << "  // producer (wave 5) alone on SIMD 1; waves 2 and 3 fed from their own SIMDs\n"
+      << "  const bool ded = (L.place & PLACE_DEDICATED) != 0u;\n"
+      << "  const u32 c = w < 4u ? w\n"
+      << "              : ded ? (w == 5u ? 0u : w == 4u ? 1u : w - 4u)\n"
+      << "                    : ((w + ((L.place & (PLACE_NEIGHBOUR | PLACE_SOLO0)) ? 3u : 0u)) & 3u);\n"
       << "  if constexpr (SSA_RING_D == 0) {\n"
       << "    SelfFeed feed;\n"
       << "    const u32 slot_rank = w * gridDim.x + blockIdx.x, n_slots = gridDim.x * 8u;\n"
@@ -462,7 +467,13 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  __syncthreads();\n"
       << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
-      << "  const bool solo0 = (L.place & PLACE_SOLO0) != 0u;\n"
+      << "  const bool solo0 = (L.place & PLACE_SOLO0) != 0u && !ded;\n"
+      << "  // event-loop slots (the wave-major static claims go in slot order, heaviest\n"
+      << "  // first): with PLACE_DEDICATED three per workgroup (waves 0, 2, 3); with\n"
+      << "  // PLACE_FEED0 wave 1, which shares its SIMD with wave 0's producer, comes last\n"
+      << "  const bool feed0 = (L.place & PLACE_FEED0) != 0u;\n"
+      << "  const u32 ev_rank = ded ? (c == 0u ? 0u : c - 1u) : feed0 ? (c == 0u ? 0u : c == 1u ? 3u : c - 1u) : c;\n"
+      << "  const u32 ev_per_wg = ded ? 3u : 4u;\n"
       << "  // wave priorities: event-loop waves 3, producers 0; PLACE_PRODUCER_FIRST:\n"
       << "  // producers 3, event-loop waves 2; PLACE_FEED0: wave 0 and its producer 3,\n"
       << "  // event-loop waves 1-3 2, the other producers 0\n"
@@ -473,7 +484,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "    // PLACE_SOLO0: event-loop wave 3 forms its own draws\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    SelfFeed feed;\n"
-      << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
+      << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
@@ -483,10 +494,10 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
-      << "  } else if (w < 4) {\n"
+      << "  } else if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
-      << "    const u32 slot_rank = c * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
+      << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * ev_per_wg;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"
       << "      lgkm_wait();\n"
@@ -499,7 +510,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
       << "    lds_st(&ctl[c].item, ~0u);\n"
-      << "  } else if (!(solo0 && w == 4u)) {   // PLACE_SOLO0: wave 4 leaves SIMD 0 to wave 0\n"
+      << "  } else if (w >= 4u && !((solo0 || ded) && w == 4u)) {   // PLACE_SOLO0, PLACE_DEDICATED: wave 4 leaves SIMD 0 to wave 0\n"
       << "    if (pr_high) __builtin_amdgcn_s_setprio(3);\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      switch (it) {\n";
@@ -944,7 +955,8 @@ int validate_desc(const ssa_run_desc *d)
     if (d->placement != 0 && (!(d->placement & SSA_PLACE_EXPLICIT) ||
                               (d->placement & ~(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER |
                                                 SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
-                                                SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST)) != 0))
+                                                SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST |
+                                                SSA_PLACE_DEDICATED_FEED0)) != 0))
         return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
@@ -1440,12 +1452,12 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     // the autotuned choice where the tuned block size is the one launched
     if (d->placement != 0)
         r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
-                                   SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST);
+                                   SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST | SSA_PLACE_DEDICATED_FEED0);
     else if (have_tuned && tuned.block == r->block)
         r->place = tuned.place;
     r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0) |
                (r->place & SSA_PLACE_SOLO_WAVE0 ? 4 : 0) | (r->place & SSA_PLACE_FEED_WAVE0 ? 8 : 0) |
-               (r->place & SSA_PLACE_PRODUCER_FIRST ? 16 : 0);
+               (r->place & SSA_PLACE_PRODUCER_FIRST ? 16 : 0) | (r->place & SSA_PLACE_DEDICATED_FEED0 ? 32 : 0);
 
     r->n_launch = n_chunks;
     if (r->noalloc) {   // direct launches, no events
@@ -1768,7 +1780,8 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     info->graph = run->graph ? 1 : 0;
     info->placement = SSA_PLACE_EXPLICIT | (run->place & 1 ? SSA_PLACE_NEIGHBOUR_PRODUCER : 0) |
                       (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0) | (run->place & 4 ? SSA_PLACE_SOLO_WAVE0 : 0) |
-                      (run->place & 8 ? SSA_PLACE_FEED_WAVE0 : 0) | (run->place & 16 ? SSA_PLACE_PRODUCER_FIRST : 0);
+                      (run->place & 8 ? SSA_PLACE_FEED_WAVE0 : 0) | (run->place & 16 ? SSA_PLACE_PRODUCER_FIRST : 0) |
+                      (run->place & 32 ? SSA_PLACE_DEDICATED_FEED0 : 0);
     return SSA_OK;
 }
 
@@ -1860,6 +1873,8 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
                                  SSA_PLACE_FEED_WAVE0);
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_SOLO_WAVE0 | SSA_PLACE_WAVE_MAJOR |
                                  SSA_PLACE_PRODUCER_FIRST);
+                // three event-loop waves, wave 0 and its producer on SIMDs of their own
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_DEDICATED_FEED0 | SSA_PLACE_WAVE_MAJOR);
             }
             for (int pl : places)
                 for (const ChunkOpt &ch : chunk_opts)

@@ -582,7 +582,17 @@ struct LaunchArgs {
 //     wave 0 (with PLACE_WAVE_MAJOR, the heaviest trajectories) keeps its draws
 //   PLACE_PRODUCER_FIRST: producer waves issue ahead of event-loop waves (a
 //     producer stops at a full ring, so it takes only what its consumer uses)
-enum { PLACE_NEIGHBOUR = 1u, PLACE_WAVE_MAJOR = 2u, PLACE_SOLO0 = 4u, PLACE_FEED0 = 8u, PLACE_PRODUCER_FIRST = 16u };
+//   PLACE_DEDICATED: three event-loop waves per workgroup; wave 0 alone on its
+//     SIMD, its producer alone on the next (waves 1 and 4 do not run), waves 2
+//     and 3 each fed by the producer on its own SIMD
+enum {
+    PLACE_NEIGHBOUR = 1u,
+    PLACE_WAVE_MAJOR = 2u,
+    PLACE_SOLO0 = 4u,
+    PLACE_FEED0 = 8u,
+    PLACE_PRODUCER_FIRST = 16u,
+    PLACE_DEDICATED = 32u
+};
 
 enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
 

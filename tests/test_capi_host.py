@@ -98,10 +98,10 @@ def test_run_descriptor_validation():
     assert _run_rc(_fields={"n_chunks": 2, "first_window": 1}) == ssa.SSA_OK
     # placement: 0, or SSA_PLACE_EXPLICIT with known flags
     every_flag = (ssa.PLACE_EXPLICIT | ssa.PLACE_NEIGHBOUR_PRODUCER | ssa.PLACE_WAVE_MAJOR | ssa.PLACE_SOLO_WAVE0 |
-                  ssa.PLACE_FEED_WAVE0 | ssa.PLACE_PRODUCER_FIRST)
+                  ssa.PLACE_FEED_WAVE0 | ssa.PLACE_PRODUCER_FIRST | ssa.PLACE_DEDICATED_FEED0)
     assert _run_rc(_fields={"placement": every_flag}) == ssa.SSA_OK
     assert _run_rc(_fields={"placement": ssa.PLACE_FEED_WAVE0}) == ssa.SSA_E_INVALID      # no SSA_PLACE_EXPLICIT
-    assert _run_rc(_fields={"placement": every_flag | 64}) == ssa.SSA_E_INVALID          # unknown flag
+    assert _run_rc(_fields={"placement": every_flag | 128}) == ssa.SSA_E_INVALID         # unknown flag
     with pytest.raises(ValueError):
         ssa.parse_mode("MIX_F8_SR")
 
