@@ -930,6 +930,12 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
     const u32 lane = lane_id();
     u32 e = 0, id = 0;
     u64 p = 0;
+    // the loop on a 64-byte boundary, as the event loops: with its first block
+    // 4 bytes past a 32-byte boundary (where the code before it happened to
+    // leave it) the heavy trajectories' producer fell behind and the open
+    // dimerisation sweep took 457-464 ms against 414-428 aligned, every other
+    // instruction the same
+    __asm__ volatile(".p2align 6");
     for (;;) {
         const u32 re = lds_ld(&ctl->req_e[lane]);
         lgkm_wait();   // a new epoch's request words were written before it
