@@ -199,7 +199,8 @@ typedef struct ssa_item {
                                           to wave 0 of workgroup 1, ...), so after a
                                           reordering window the heaviest trajectories share
                                           one wave per workgroup                            */
-#define SSA_PLACE_SOLO_WAVE0 8         /* 512-thread workgroups: event-loop wave 0 runs with its
+#define SSA_PLACE_SOLO_WAVE0 8         /* 512-thread workgroups, one-item launches (SSA_E_INVALID
+                                          otherwise): event-loop wave 0 runs with its
                                           SIMD to itself (producers feed the next SIMD's wave,
                                           event-loop wave 3 forms its own draws, wave 4 does
                                           not run); with SSA_PLACE_WAVE_MAJOR the heaviest

@@ -467,7 +467,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  __syncthreads();\n"
       << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
-      << "  const bool solo0 = (L.place & PLACE_SOLO0) != 0u && !ded;\n"
+      << "  const bool solo0 = SSA_N_ITEMS == 1 && (L.place & PLACE_SOLO0) != 0u && !ded;\n"
       << "  // event-loop slots (the wave-major static claims go in slot order, heaviest\n"
       << "  // first): with PLACE_DEDICATED three per workgroup (waves 0, 2, 3); with\n"
       << "  // PLACE_FEED0 wave 1, which shares its SIMD with wave 0's producer, comes last\n"
@@ -480,8 +480,11 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "  const bool pfirst = (L.place & PLACE_PRODUCER_FIRST) != 0u;\n"
       << "  const bool ev_low = pfirst || ((L.place & PLACE_FEED0) != 0u && c != 0u);\n"
       << "  const bool pr_high = pfirst || ((L.place & PLACE_FEED0) != 0u && c == 0u);\n"
+      << "  // PLACE_SOLO0 (one-item launches): event-loop wave 3 forms its own draws; a\n"
+      << "  // second copy of the event loop per network, so it is compiled only for one\n"
+      << "  // network (several networks' copies would crowd the instruction cache)\n"
+      << "#if SSA_N_ITEMS == 1\n"
       << "  if (w < 4 && solo0 && c == 3u) {\n"
-      << "    // PLACE_SOLO0: event-loop wave 3 forms its own draws\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    SelfFeed feed;\n"
       << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * 4u;\n"
@@ -494,7 +497,9 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
-      << "  } else if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
+      << "  } else\n"
+      << "#endif\n"
+      << "  if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
       << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
       << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * ev_per_wg;\n"
@@ -958,6 +963,8 @@ int validate_desc(const ssa_run_desc *d)
                                                 SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST |
                                                 SSA_PLACE_DEDICATED_FEED0)) != 0))
         return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
+    if ((d->placement & SSA_PLACE_SOLO_WAVE0) && d->n_items > 1)
+        return fail(SSA_E_INVALID, "SSA_PLACE_SOLO_WAVE0 needs a one-item launch");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
     uint64_t total = 0;

@@ -102,6 +102,14 @@ def test_run_descriptor_validation():
     assert _run_rc(_fields={"placement": every_flag}) == ssa.SSA_OK
     assert _run_rc(_fields={"placement": ssa.PLACE_FEED_WAVE0}) == ssa.SSA_E_INVALID      # no SSA_PLACE_EXPLICIT
     assert _run_rc(_fields={"placement": every_flag | 128}) == ssa.SSA_E_INVALID         # unknown flag
+    # wave 0 alone on its SIMD: one-item launches only
+    m2 = ssa.Model(wl.birth_death())
+    two = [{"model": m2, "x0": [0], "n_traj": 10}, {"model": m2, "x0": [1], "n_traj": 10}]
+    d2, keep2 = ssa._desc(two, 1.0, [0.5, 1.0], 1, "FP64")
+    d2.placement = ssa.PLACE_EXPLICIT | ssa.PLACE_SOLO_WAVE0
+    assert ssa.lib().ssa_prepare(ctypes.byref(d2)) == ssa.SSA_E_INVALID
+    d2.placement = ssa.PLACE_EXPLICIT | ssa.PLACE_DEDICATED_FEED0
+    assert ssa.lib().ssa_prepare(ctypes.byref(d2)) == ssa.SSA_OK
     with pytest.raises(ValueError):
         ssa.parse_mode("MIX_F8_SR")
 
