@@ -216,6 +216,13 @@ typedef struct ssa_item {
                                           next, the other two fed from their own SIMDs (with
                                           SSA_PLACE_WAVE_MAJOR: the heaviest trajectories on
                                           wave 0, never short of draws)                    */
+#define SSA_PLACE_TWO_FEED0 128        /* with SSA_PLACE_DEDICATED_FEED0, one-item launches
+                                          (SSA_E_INVALID otherwise): two producer waves share
+                                          wave 0's draws, one the even and one the odd event
+                                          indices (a lone event loop on the conversion path
+                                          uses draws faster than one producer makes them);
+                                          no effect where the draw ring holds fewer than 4
+                                          slots (the largest networks)                     */
 
 typedef struct ssa_run_desc {
     const ssa_item *items;

@@ -259,14 +259,16 @@ std::string gen_model(const Model &md, int idx, uint64_t record_mask)
       << ";\n"
       << "  static constexpr u64 REC = " << record_mask << "ull;  // reactions whose firings are recorded\n"
       << "  static constexpr int LO_MAX = " << lo_max << ";  // largest reactant order of a species\n"
-      << "  // some count below its species' largest reactant order (a zero guard may apply)\n"
+      << "  // some count below its species' largest reactant order (a zero guard may apply);\n"
+      << "  // counts are never negative, so x - lo < 0 exactly when x < lo, and the OR of\n"
+      << "  // the differences is negative when one of them is (one compare for the wave)\n"
       << "  __device__ static __forceinline__ bool below(const i32 (&x)[N]) {\n"
       << "    (void)x;\n"
-      << "    return false";
+      << "    return (0";
     for (int s = 0; s < md.N; ++s)
         if (lo[(size_t)s] > 0)
-            o << " || x[" << s << "] < " << lo[(size_t)s];
-    o << ";\n  }\n"
+            o << " | (x[" << s << "] - " << lo[(size_t)s] << ")";
+    o << ") < 0;\n  }\n"
       << "  // max over species of count - largest order, as unsigned (a count below\n"
       << "  // its order wraps to a large value)\n"
       << "  __device__ static __forceinline__ u32 range_key(const i32 (&x)[N]) {\n"
@@ -462,12 +464,17 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "    ctl[c].done[lane] = 0u;\n"
       << "    ctl[c].item = 0u;\n"
       << "  } else {\n"
-      << "    ctl[c].made[lane] = 0u;\n"
+      << "    ctl[c].made[0][lane] = 0u;\n"
+      << "    ctl[c].made[1][lane] = 0u;\n"
       << "  }\n"
       << "  __syncthreads();\n"
       << "  u32 *my_ring = ring + c * (SSA_RING_D * SSA_RING_NW * 64);\n"
       << "  u32 it = (blockIdx.x * 4u + c) % SSA_N_ITEMS;\n"
       << "  const bool solo0 = SSA_N_ITEMS == 1 && (L.place & PLACE_SOLO0) != 0u && !ded;\n"
+      << "  // PLACE_TWO0 (with PLACE_DEDICATED, one-item launches): wave 1 is a second\n"
+      << "  // producer of wave 0; waves 5 and 1 make its draws of even and odd index\n"
+      << "  // (a ring of fewer than 4 slots, for the largest networks, keeps one producer)\n"
+      << "  const bool two = SSA_N_ITEMS == 1 && SSA_RING_D >= 4 && ded && (L.place & PLACE_TWO0) != 0u;\n"
       << "  // event-loop slots (the wave-major static claims go in slot order, heaviest\n"
       << "  // first): with PLACE_DEDICATED three per workgroup (waves 0, 2, 3); with\n"
       << "  // PLACE_FEED0 wave 1, which shares its SIMD with wave 0's producer, comes last\n"
@@ -497,11 +504,16 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
       << "    }\n"
+      << "  } else if (two && (w == 1u || w == 5u)) {\n"
+      << "    if constexpr (SSA_RING_D >= 4) {\n"
+      << "      if (pfirst || feed0) __builtin_amdgcn_s_setprio(3);\n"
+      << "      produce_item<PrecRun, Md0, SSA_RING_D, SSA_RING_NW, 2>(L, L.item[0], &ctl[0], ring, 0u, w == 1u ? 1u : 0u);\n"
+      << "    }\n"
       << "  } else\n"
       << "#endif\n"
       << "  if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, two && c == 0u ? 0x100u : 0u};\n"
       << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * ev_per_wg;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"
@@ -521,7 +533,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      switch (it) {\n";
     for (size_t i = 0; i < models.size(); ++i)
         o << "      case " << i << ": produce_item<PrecRun, Md" << i
-          << ", SSA_RING_D, SSA_RING_NW>(L, L.item[" << i << "], &ctl[c], my_ring, i); break;\n";
+          << ", SSA_RING_D, SSA_RING_NW, 1>(L, L.item[" << i << "], &ctl[c], my_ring, i, 0u); break;\n";
     o << "      default: break;\n"
       << "      }\n"
       << "      it = it + 1 == SSA_N_ITEMS ? 0 : it + 1;\n"
@@ -961,10 +973,12 @@ int validate_desc(const ssa_run_desc *d)
                               (d->placement & ~(SSA_PLACE_EXPLICIT | SSA_PLACE_NEIGHBOUR_PRODUCER |
                                                 SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
                                                 SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST |
-                                                SSA_PLACE_DEDICATED_FEED0)) != 0))
+                                                SSA_PLACE_DEDICATED_FEED0 | SSA_PLACE_TWO_FEED0)) != 0))
         return fail(SSA_E_INVALID, "placement must be 0 or SSA_PLACE_EXPLICIT with SSA_PLACE_* flags");
     if ((d->placement & SSA_PLACE_SOLO_WAVE0) && d->n_items > 1)
         return fail(SSA_E_INVALID, "SSA_PLACE_SOLO_WAVE0 needs a one-item launch");
+    if ((d->placement & SSA_PLACE_TWO_FEED0) && (d->n_items > 1 || !(d->placement & SSA_PLACE_DEDICATED_FEED0)))
+        return fail(SSA_E_INVALID, "SSA_PLACE_TWO_FEED0 needs a one-item launch and SSA_PLACE_DEDICATED_FEED0");
     if (d->n_chunks > 1 && d->first_window > 0 && d->first_window > d->n_snap - (d->n_chunks - 1))
         return fail(SSA_E_INVALID, "first_window leaves no snapshot row for a later chunk");
     uint64_t total = 0;
@@ -1459,12 +1473,14 @@ int run_impl(const ssa_run_desc *d, ssa_run *r)
     // the autotuned choice where the tuned block size is the one launched
     if (d->placement != 0)
         r->place = d->placement & (SSA_PLACE_NEIGHBOUR_PRODUCER | SSA_PLACE_WAVE_MAJOR | SSA_PLACE_SOLO_WAVE0 |
-                                   SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST | SSA_PLACE_DEDICATED_FEED0);
+                                   SSA_PLACE_FEED_WAVE0 | SSA_PLACE_PRODUCER_FIRST | SSA_PLACE_DEDICATED_FEED0 |
+                                   SSA_PLACE_TWO_FEED0);
     else if (have_tuned && tuned.block == r->block)
         r->place = tuned.place;
     r->place = (r->place & SSA_PLACE_NEIGHBOUR_PRODUCER ? 1 : 0) | (r->place & SSA_PLACE_WAVE_MAJOR ? 2 : 0) |
                (r->place & SSA_PLACE_SOLO_WAVE0 ? 4 : 0) | (r->place & SSA_PLACE_FEED_WAVE0 ? 8 : 0) |
-               (r->place & SSA_PLACE_PRODUCER_FIRST ? 16 : 0) | (r->place & SSA_PLACE_DEDICATED_FEED0 ? 32 : 0);
+               (r->place & SSA_PLACE_PRODUCER_FIRST ? 16 : 0) | (r->place & SSA_PLACE_DEDICATED_FEED0 ? 32 : 0) |
+               (r->place & SSA_PLACE_TWO_FEED0 ? 64 : 0);
 
     r->n_launch = n_chunks;
     if (r->noalloc) {   // direct launches, no events
@@ -1788,7 +1804,7 @@ int ssa_run_info_get(const ssa_run *run, ssa_run_info *info)
     info->placement = SSA_PLACE_EXPLICIT | (run->place & 1 ? SSA_PLACE_NEIGHBOUR_PRODUCER : 0) |
                       (run->place & 2 ? SSA_PLACE_WAVE_MAJOR : 0) | (run->place & 4 ? SSA_PLACE_SOLO_WAVE0 : 0) |
                       (run->place & 8 ? SSA_PLACE_FEED_WAVE0 : 0) | (run->place & 16 ? SSA_PLACE_PRODUCER_FIRST : 0) |
-                      (run->place & 32 ? SSA_PLACE_DEDICATED_FEED0 : 0);
+                      (run->place & 32 ? SSA_PLACE_DEDICATED_FEED0 : 0) | (run->place & 64 ? SSA_PLACE_TWO_FEED0 : 0);
     return SSA_OK;
 }
 
@@ -1882,6 +1898,9 @@ int ssa_autotune(const ssa_run_desc *desc, ssa_tune_result *res)
                                  SSA_PLACE_PRODUCER_FIRST);
                 // three event-loop waves, wave 0 and its producer on SIMDs of their own
                 places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_DEDICATED_FEED0 | SSA_PLACE_WAVE_MAJOR);
+                // the same with two producers for wave 0
+                places.push_back(SSA_PLACE_EXPLICIT | SSA_PLACE_DEDICATED_FEED0 | SSA_PLACE_WAVE_MAJOR |
+                                 SSA_PLACE_TWO_FEED0);
             }
             for (int pl : places)
                 for (const ChunkOpt &ch : chunk_opts)

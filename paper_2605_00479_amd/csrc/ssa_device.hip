@@ -585,13 +585,19 @@ struct LaunchArgs {
 //   PLACE_DEDICATED: three event-loop waves per workgroup; wave 0 alone on its
 //     SIMD, its producer alone on the next (waves 1 and 4 do not run), waves 2
 //     and 3 each fed by the producer on its own SIMD
+//   PLACE_TWO0 (with PLACE_DEDICATED, one-item launches): wave 1 runs as a
+//     second producer of wave 0 on SIMD 1; waves 5 and 1 make wave 0's draws
+//     of even and odd event index. A lone event-loop wave on the conversion
+//     path uses its draws faster than one producer wave makes them with their
+//     conversion fields; two waves on one SIMD also hide each other's latency.
 enum {
     PLACE_NEIGHBOUR = 1u,
     PLACE_WAVE_MAJOR = 2u,
     PLACE_SOLO0 = 4u,
     PLACE_FEED0 = 8u,
     PLACE_PRODUCER_FIRST = 16u,
-    PLACE_DEDICATED = 32u
+    PLACE_DEDICATED = 32u,
+    PLACE_TWO0 = 64u
 };
 
 enum { ST_DONE = 0, ST_ABSORBED = 1, ST_OVERFLOW = 2, ST_CAPPED = 3, ST_SUSPENDED = 255 };
@@ -746,7 +752,11 @@ struct RingWords {
 //          has not read yet;
 //   made   producer -> consumer: counter word of the first draw not made yet;
 //          draws [made - D, made) of epoch e are in the ring (the consumer
-//          resets it at a claim, before publishing the epoch).
+//          resets it at a claim, before publishing the epoch). With two
+//          producers for one consumer (PLACE_TWO0), producer k makes the draws
+//          of odd (k = 1) or even (k = 0) event index and publishes made[k]:
+//          its draws of that parity in [made[k] - D, made[k]) are in the ring,
+//          and the consumer reads the made word of its next draw's parity.
 //   convw  consumer -> producer: the lane's counts need conversion fields
 //          (reset at a claim); the producer then also forms each draw's
 //          conversion fields, stores them after the draw's words, and marks
@@ -758,7 +768,7 @@ struct RingWords {
 // it loads ring words, and for its ring loads before it updates done.
 // --------------------------------------------------------------------------
 struct RingCtl {
-    u32 made[64];
+    u32 made[2][64];   // [parity class][lane]; class 1 only with two producers
     u32 done[64];
     u32 req_e[64];
     u32 req_id[64];
@@ -799,6 +809,8 @@ struct RingFeed {
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
     u32 dw;         // counter word of the draw the lane takes next (event n + 1)
+    u32 cmask;      // 0x100 with two producers (a made word's byte offset is the
+                    // parity bit of the event index, bit 8 of a counter word), else 0
 
     // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
     // made is reset to "nothing made in this epoch" before the epoch is
@@ -809,7 +821,8 @@ struct RingFeed {
         eb = eb % 255u + 1u;
         dw = ((u32)(n + 1) << 8) | eb;
         lds_st(&ctl->done[lane], dw);
-        lds_st(&ctl->made[lane], dw);
+        lds_st(&ctl->made[0][lane], dw);
+        lds_st(&ctl->made[1][lane], dw);
         lds_st(&ctl->req_id[lane], id);
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
@@ -849,7 +862,11 @@ struct RingFeed {
         return cp;
     }
 
-    __device__ u32 made_word() const { return lds_ld(&ctl->made[lane]); }
+    // the made word of the parity class of the draw the lane takes next (dw)
+    __device__ u32 made_word() const
+    {
+        return lds_ld((const u32 *)((const char *)&ctl->made[0][lane] + (dw & cmask)));
+    }
 
     // slot of the draw with counter word dw: its index mod D, times the 256
     // bytes of a slot's word, is dw's index bits [8, 8 + log2 D) in place
@@ -917,16 +934,20 @@ struct RingFeed {
 // (a lane with fewer free slots stores only those). The shape is measured:
 // with the event loop and this wave sharing a SIMD, 6 draws from 6 free slots
 // of 16 keep the ring ahead for binary32 and 16-bit draws, 8 from 4 for binary64.
+// STRIDE 2: one of two producers of the consumer, making the draws whose event
+// index has parity cls (PLACE_TWO0); each then holds at most D / 2 draws of
+// the ring, and a batch of 4 from 4 free places keeps its half ahead.
 // Returns once the consumer has moved past item `seq`.
-template <class P, class Md, int D, int NWMAX>
-__device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ctl, u32 *ring, u32 seq)
+template <class P, class Md, int D, int NWMAX, int STRIDE>
+__device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ctl, u32 *ring, u32 seq, u32 cls)
 {
     typedef Slots<P, Md> S;
     typedef DrawIO<P, S::NSLOT> IO;
     typedef ConvRing<P, Md> CR;
     static_assert(!CR::ON || IO::NP >= 3, "the conversion mark lives in the third pool word");
-    constexpr int BATCH = D >= 16 ? (P::WIDE ? 8 : 6) : (D >= 2 ? D / 2 : 1);
-    constexpr int START = P::WIDE && BATCH > 4 ? 4 : BATCH;
+    static_assert(STRIDE == 1 || (STRIDE == 2 && D >= 4), "two producers share a ring of at least 4 slots");
+    constexpr int BATCH = STRIDE == 2 ? (D >= 16 ? 4 : D / 4) : D >= 16 ? (P::WIDE ? 8 : 6) : (D >= 2 ? D / 2 : 1);
+    constexpr int START = STRIDE == 2 ? BATCH : P::WIDE && BATCH > 4 ? 4 : BATCH;
     const u32 lane = lane_id();
     u32 e = 0, id = 0;
     u64 p = 0;
@@ -950,17 +971,27 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
             e = re;
             id = lds_ld(&ctl->req_id[lane]);
             p = (((u64)lds_ld(&ctl->req_hi[lane]) << 32) | lds_ld(&ctl->req_lo[lane])) + 1;
+            if constexpr (STRIDE == 2)
+                p += ((u32)p ^ cls) & 1u;   // the first index of this producer's parity
         }
         // draws made and not yet read: p - done, as a signed 24-bit difference. The
         // event-loop lane may be ahead (it forms draws itself until the ring holds
-        // them, e.g. right after a claim): then skip to its next unread draw.
+        // them, e.g. right after a claim): then skip to its next unread draw (of
+        // this producer's parity).
         const bool mine = e != 0 && (dw & 0xFFu) == e;
         i32 ahead = (i32)(((u32)p << 8) - (dw & ~0xFFu)) >> 8;
         if (mine && ahead < 0) {
             p += (u64)(u32)(-ahead);
             ahead = 0;
+            if constexpr (STRIDE == 2) {
+                const u32 fix = ((u32)p ^ cls) & 1u;
+                p += fix;
+                ahead = (i32)fix;
+            }
         }
-        const u32 room = (mine && ahead < D) ? (u32)(D - ahead) : 0u;
+        // places p, p + 1, ... below done + D; this producer's draws among them
+        const u32 span = (mine && ahead < D) ? (u32)(D - ahead) : 0u;
+        const u32 room = STRIDE == 2 ? (span + 1u) >> 1 : span;
         if (__builtin_amdgcn_ballot_w64(room >= (u32)START) == 0) {
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -968,7 +999,7 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
         Draw<P, S::NSLOT> d[BATCH];
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
-            d[b] = make_draw<P, S::NSLOT, S::LOG>(p + (u64)b, id, L.seed_lo, L.seed_hi);
+            d[b] = make_draw<P, S::NSLOT, S::LOG>(p + (u64)(STRIDE * b), id, L.seed_lo, L.seed_hi);
         // formed here, every one: left to the guarded stores below, each
         // would be formed in a block of its own, one chain after another
 #pragma unroll
@@ -988,7 +1019,7 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
                 ConvPool<Md::NCONV, P::SR_B> cv[BATCH];
 #pragma unroll
                 for (int b = 0; b < BATCH; ++b)
-                    cv[b] = make_conv<Md::NCONV, P::SR_B>(p + (u64)b, id, L.seed_lo, L.seed_hi);
+                    cv[b] = make_conv<Md::NCONV, P::SR_B>(p + (u64)(STRIDE * b), id, L.seed_lo, L.seed_hi);
 #pragma unroll
                 for (int b = 0; b < BATCH; ++b) {
 #pragma unroll
@@ -999,7 +1030,7 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 #pragma unroll
                 for (int b = 0; b < BATCH; ++b)
                     if ((u32)b < room) {
-                        u32 *w = ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * 64 + lane;
+                        u32 *w = ring + ((u32)(p + (u64)(STRIDE * b)) & (u32)(D - 1)) * 64 + lane;
 #pragma unroll
                         for (int q = 0; q < CR::NW; ++q)
                             w[(IO::NW + q) * D * 64] = cv[b].w[q];
@@ -1009,12 +1040,12 @@ __device__ void produce_item(const LaunchArgs &L, const ItemArgs &I, RingCtl *ct
 #pragma unroll
         for (int b = 0; b < BATCH; ++b)
             if ((u32)b < room)
-                IO::template store<D * 64>(ring + ((u32)(p + (u64)b) & (u32)(D - 1)) * 64 + lane, d[b]);
+                IO::template store<D * 64>(ring + ((u32)(p + (u64)(STRIDE * b)) & (u32)(D - 1)) * 64 + lane, d[b]);
         const u32 k = room < (u32)BATCH ? room : (u32)BATCH;
         lgkm_wait();
         if (k != 0u) {
-            lds_st(&ctl->made[lane], ((u32)(p + k) << 8) | e);
-            p += k;
+            p += (u64)(STRIDE * k);
+            lds_st(&ctl->made[STRIDE == 2 ? cls : 0u][lane], ((u32)p << 8) | e);
         }
     }
     (void)I;
@@ -1051,7 +1082,10 @@ __host__ __device__ constexpr int cmax(int a, int b)
 // The event loop runs one straight-line loop per version and leaves it when
 // the updated state needs another, so a wave that stays in one version (a
 // long trajectory far above the exact-integer limit) takes no branch but the
-// loop's own each event.
+// loop's own each event. The loop test is one ballot for the states the
+// version cannot compute; a move to a cheaper version waits for the next
+// event that takes the rare path (a snapshot crossing, a fallback selection,
+// a draw the producer has not made), which costs time, never results.
 // --------------------------------------------------------------------------
 enum { VER_EXACT = 0, VER_GUARD = 1, VER_CONV = 2, VER_CONV_NG = 3 };
 
@@ -1091,22 +1125,33 @@ struct Versions {
         }
     }
 
-    // the state still needs version V (one wave test where it can be decided by one)
+    // Lanes whose updated state version V cannot compute: a count above the
+    // exact-integer limit where V converts without rounding, a count below a
+    // reactant order where V has no zero guard. VER_CONV computes every state.
+    // One ballot per version; leaving for a cheaper version (a state that no
+    // longer needs V's extra work) is optional, and is tested on the rare path.
     template <int V>
-    __device__ static __forceinline__ bool still(const i32 (&x)[Md::N], u64 act)
+    __device__ static __forceinline__ u64 must_leave(const i32 (&x)[Md::N], u64 act)
     {
         if constexpr (V == VER_EXACT) {
             if constexpr (CONV)
-                return (act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX))) == 0;
+                return act & lanes(Md::range_key(x) > (u32)(P::EXACT_INT - Md::LO_MAX));
             else if constexpr (GUARD)
-                return (act & lanes(Md::below(x))) == 0;
+                return act & lanes(Md::below(x));
             else
-                return true;
+                return 0;
+        } else if constexpr (V == VER_GUARD) {
+            if constexpr (CONV)
+                return act & lanes(max_count(x) > (u32)P::EXACT_INT);
+            else
+                return 0;
         } else if constexpr (V == VER_CONV_NG) {
-            return ((act & lanes(max_count(x) > (u32)P::EXACT_INT)) != 0) &&
-                   (!GUARD || (act & lanes(Md::below(x))) == 0);
+            if constexpr (GUARD)
+                return act & lanes(Md::below(x));
+            else
+                return 0;
         } else {
-            return of(x, act) == V;
+            return 0;
         }
     }
 };
@@ -1257,13 +1302,9 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
             Tm t_new = 0;
             bool a_ok = false, m_ok = true, fire = false;
             u64 stop_lanes;
-            // the event loop's first instruction on a 64-byte boundary: where the
-            // taken back-branch lands decides how many instruction-fetch lines an
-            // event spans (the same loop measured up to 5% apart between offsets;
-            // the padding runs once, before the loop)
-            // One event step in propensity version V; returns whether the next
-            // event needs the same version.
-            auto step = [&](auto vtag) __attribute__((always_inline)) -> bool {
+            // One event step in propensity version V; returns the lanes (or, for a
+            // cheaper version, every lane) that make the wave choose its version again.
+            auto step = [&](auto vtag) __attribute__((always_inline)) -> u64 {
                 constexpr int V = decltype(vtag)::value;
                 // ---- draws: cur belongs to event n; event n+1's is formed (or
                 // taken from the producer's ring) alongside
@@ -1281,6 +1322,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 // no conversion stream is drawn. A mass-action propensity is
                 // zero when a count is below its order; with every count at or
                 // above its species' largest order no guard can apply.
+                u64 cheaper = 0;
                 T a[M];
                 if constexpr (V == VER_EXACT) {
                     Md::template propensities<P, VS::CONV, false>(x, c, hill, a, pool, NoConv());
@@ -1383,6 +1425,10 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                         if (miss != 0)
                             feed.template self_draw<P, NSLOT, SLOT_LOG>(nxt, miss, n + 1, id, L.seed_lo, L.seed_hi);
                     }
+                    // a cheaper version may serve the state now: leave after this event
+                    // and choose again (a state V cannot compute is caught after the update)
+                    if constexpr (V != VER_EXACT)
+                        cheaper = lanes(VS::of(x, act) != V);
                 }
                 fire = active && a_ok && t_new <= t_stop;
                 const u64 fire_lanes = ok_lanes & lanes(t_new <= t_stop);
@@ -1406,7 +1452,7 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
                 if constexpr (CONV_RING)
                     conv_cur = conv_nxt;
                 stop_lanes = act & (~fire_lanes | lanes(n == n_stop));
-                return VS::template still<V>(x, act);
+                return VS::template must_leave<V>(x, act) | cheaper;
             };
             // one straight-line loop per version; its first instruction on a
             // 64-byte boundary (where the taken back-branch lands decides how
@@ -1414,34 +1460,34 @@ __device__ void run_item(const LaunchArgs &L, const ItemArgs &I, F &feed, u32 sl
             // measured up to 5% apart between offsets; the padding runs once)
             int ver = VS::of(x, act);
             for (;;) {
-                bool stay;
+                u64 leave;
                 if constexpr (CONV_RING)
                     feed.request_conv(ver >= VER_CONV ? 1u : 0u);
                 if (ver == VER_EXACT) {
                     __asm__ volatile(".p2align 6");
                     do {
-                        stay = step(IC<VER_EXACT>());
-                    } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                        leave = step(IC<VER_EXACT>());
+                    } while (__builtin_expect((stop_lanes | leave) == 0, 1));
                 } else if (VS::GUARD && ver == VER_GUARD) {
                     if constexpr (VS::GUARD) {
                         __asm__ volatile(".p2align 6");
                         do {
-                            stay = step(IC<VER_GUARD>());
-                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                            leave = step(IC<VER_GUARD>());
+                        } while (__builtin_expect((stop_lanes | leave) == 0, 1));
                     }
                 } else if (VS::CONV && ver == VER_CONV_NG) {
                     if constexpr (VS::CONV) {
                         __asm__ volatile(".p2align 6");
                         do {
-                            stay = step(IC<VER_CONV_NG>());
-                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                            leave = step(IC<VER_CONV_NG>());
+                        } while (__builtin_expect((stop_lanes | leave) == 0, 1));
                     }
                 } else {
                     if constexpr (VS::CONV && VS::GUARD) {
                         __asm__ volatile(".p2align 6");
                         do {
-                            stay = step(IC<VER_CONV>());
-                        } while (__builtin_expect(stop_lanes == 0, 1) && __builtin_expect(stay, 1));
+                            leave = step(IC<VER_CONV>());
+                        } while (__builtin_expect((stop_lanes | leave) == 0, 1));
                     }
                 }
                 if (stop_lanes != 0)

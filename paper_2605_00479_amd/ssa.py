@@ -268,7 +268,7 @@ def _desc(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_c
 
 
 (PLACE_AUTO, PLACE_EXPLICIT, PLACE_NEIGHBOUR_PRODUCER, PLACE_WAVE_MAJOR, PLACE_SOLO_WAVE0,
- PLACE_FEED_WAVE0, PLACE_PRODUCER_FIRST, PLACE_DEDICATED_FEED0) = 0, 1, 2, 4, 8, 16, 32, 64
+ PLACE_FEED_WAVE0, PLACE_PRODUCER_FIRST, PLACE_DEDICATED_FEED0, PLACE_TWO_FEED0) = 0, 1, 2, 4, 8, 16, 32, 64, 128
 
 
 def ssa_ensemble_run(items, t_end, snap_t, seed, mode, *, max_events=0, traj_id_base=0, n_chunks=1,

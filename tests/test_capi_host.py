@@ -98,10 +98,12 @@ def test_run_descriptor_validation():
     assert _run_rc(_fields={"n_chunks": 2, "first_window": 1}) == ssa.SSA_OK
     # placement: 0, or SSA_PLACE_EXPLICIT with known flags
     every_flag = (ssa.PLACE_EXPLICIT | ssa.PLACE_NEIGHBOUR_PRODUCER | ssa.PLACE_WAVE_MAJOR | ssa.PLACE_SOLO_WAVE0 |
-                  ssa.PLACE_FEED_WAVE0 | ssa.PLACE_PRODUCER_FIRST | ssa.PLACE_DEDICATED_FEED0)
+                  ssa.PLACE_FEED_WAVE0 | ssa.PLACE_PRODUCER_FIRST | ssa.PLACE_DEDICATED_FEED0 | ssa.PLACE_TWO_FEED0)
     assert _run_rc(_fields={"placement": every_flag}) == ssa.SSA_OK
     assert _run_rc(_fields={"placement": ssa.PLACE_FEED_WAVE0}) == ssa.SSA_E_INVALID      # no SSA_PLACE_EXPLICIT
-    assert _run_rc(_fields={"placement": every_flag | 128}) == ssa.SSA_E_INVALID         # unknown flag
+    assert _run_rc(_fields={"placement": every_flag | 256}) == ssa.SSA_E_INVALID         # unknown flag
+    # two producers for wave 0: only with the dedicated placement
+    assert _run_rc(_fields={"placement": ssa.PLACE_EXPLICIT | ssa.PLACE_TWO_FEED0}) == ssa.SSA_E_INVALID
     # wave 0 alone on its SIMD: one-item launches only
     m2 = ssa.Model(wl.birth_death())
     two = [{"model": m2, "x0": [0], "n_traj": 10}, {"model": m2, "x0": [1], "n_traj": 10}]
@@ -110,6 +112,8 @@ def test_run_descriptor_validation():
     assert ssa.lib().ssa_prepare(ctypes.byref(d2)) == ssa.SSA_E_INVALID
     d2.placement = ssa.PLACE_EXPLICIT | ssa.PLACE_DEDICATED_FEED0
     assert ssa.lib().ssa_prepare(ctypes.byref(d2)) == ssa.SSA_OK
+    d2.placement = ssa.PLACE_EXPLICIT | ssa.PLACE_DEDICATED_FEED0 | ssa.PLACE_TWO_FEED0
+    assert ssa.lib().ssa_prepare(ctypes.byref(d2)) == ssa.SSA_E_INVALID
     with pytest.raises(ValueError):
         ssa.parse_mode("MIX_F8_SR")
 

@@ -523,10 +523,10 @@ def test_producer_waves_event_record(gpu, orc):
 # Placements of the 512-thread launch (producer on the event-loop wave's own
 # SIMD or the next one, wave-major first claims, wave 0 alone on its SIMD,
 # wave priorities, three event-loop waves with wave 0's producer alone on a
-# SIMD): only where and when work runs changes, so results are the oracle's in
-# every one.
+# SIMD, two producers splitting wave 0's draws by event parity): only where and
+# when work runs changes, so results are the oracle's in every one.
 # ---------------------------------------------------------------------------
-PLACEMENTS = [3, 5, 7, 9, 13, 29, 45, 19, 35, 65, 69, 85, 101]
+PLACEMENTS = [3, 5, 7, 9, 13, 29, 45, 19, 35, 65, 69, 85, 101, 197, 213]
 
 
 @pytest.mark.parametrize("placement", PLACEMENTS)
@@ -540,7 +540,7 @@ def test_placements_schlogl(gpu, orc, mode, placement):
     assert run.info()["placement"] == placement
 
 
-@pytest.mark.parametrize("placement", [1, 7, 13, 29, 45, 69])
+@pytest.mark.parametrize("placement", [1, 7, 13, 29, 45, 69, 197, 213])
 def test_placements_dimer_sets_with_conversion_fields(gpu, orc, placement):
     """Per-lane parameter sets whose counts pass the fp16 exact-integer limit
     (2048): the producers form the conversion fields for those lanes, under

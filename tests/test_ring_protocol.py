@@ -20,6 +20,11 @@ the current draw's fields from its slot (before it publishes done) if that
 draw came from the ring with the mark, and forms them itself otherwise; fields
 it reads must be its own draw's.
 
+Two producers (PLACE_TWO0): producer k makes only the draws of event index
+with parity k and publishes its own made word; the lane reads the made word of
+its next draw's parity. The same checks apply, with both producers scheduled
+against the lane.
+
 This checks the protocol as designed; the GPU tests check the kernel's results.
 """
 import random
@@ -47,7 +52,7 @@ def rotr8(v):
 
 class Shared:
     def __init__(self, D):
-        self.made = 0
+        self.made = [0, 0]          # [parity class]; class 1 only with two producers
         self.done = 0
         self.req_e = 0
         self.req_id = 0
@@ -58,10 +63,11 @@ class Shared:
         self.conv = [None] * D      # (trajectory, event) of the conversion fields
 
 
-def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
+def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0, two=False):
     """Generator: one step per LDS operation (plus the local work between).
     p_need: per trajectory, the chance that its counts pass the exact-integer
-    limit (from a random event on, until it ends)."""
+    limit (from a random event on, until it ends). two: the made word is the
+    one of the next draw's parity class."""
     eb = 0
     for uid in range(1, n_traj + 1):     # uid: the trajectory's id (draws are keyed by it)
         n = start_n(rng)
@@ -71,7 +77,8 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
         dw = word(n + 1, eb)
         sh.done = dw
         yield
-        sh.made = dw
+        sh.made[0] = dw
+        sh.made[1] = dw
         yield
         sh.req_id, sh.req_lo, sh.req_hi = uid, n & 0xFFFFFFFF, n >> 32
         sh.convw = 0
@@ -83,7 +90,7 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
         cur_mark = False                                      # the claim forms its draw itself
         for ev in range(length):
             want = n + 1
-            mw = sh.made                                      # top of the event
+            mw = sh.made[(dw >> 8) & 1 if two else 0]         # top of the event
             yield
             if need_from is not None and ev == need_from:     # entering a conversion version
                 sh.convw = 1                                  # the request word, once
@@ -114,9 +121,10 @@ def consumer(sh, D, rng, n_traj, start_n, log, lengths, p_need=0.0):
     log["consumer_done"] = True
 
 
-def producer(sh, D, batch, rng, log, skip=True, start=1):
+def producer(sh, D, batch, rng, log, skip=True, start=1, cls=0, stride=1):
     """start: free slots before a batch begins (in the kernel another lane's
-    free slots may start it, so start = 1 covers every lane's case)."""
+    free slots may start it, so start = 1 covers every lane's case).
+    stride 2: one of two producers, making the draws of parity cls."""
     e, p, uid = 0, 0, 0
     while not log.get("consumer_done"):
         re = sh.req_e
@@ -127,6 +135,8 @@ def producer(sh, D, batch, rng, log, skip=True, start=1):
             e = re
             uid = sh.req_id
             p = ((sh.req_hi << 32) | sh.req_lo) + 1
+            if stride == 2:
+                p += (p ^ cls) & 1
             yield
         cw = sh.convw
         yield
@@ -136,23 +146,29 @@ def producer(sh, D, batch, rng, log, skip=True, start=1):
             if mine and ahead < 0:
                 p += -ahead
                 ahead = 0
+                if stride == 2:
+                    fix = (p ^ cls) & 1
+                    p += fix
+                    ahead = fix
         else:   # the unsigned distance without the skip: behind reads as a full ring
             ahead = (((p << 8) - (dw & ~0xFF)) & M32) >> 8
-        room = D - ahead if (mine and ahead < D) else 0
+        span = D - ahead if (mine and ahead < D) else 0
+        room = (span + 1) // 2 if stride == 2 else span
         if room < start:
             yield                                             # sleep
             continue
         k = min(room, batch)
         mark = bool(mine and cw)
         for b in range(k):
+            q = p + stride * b
             if mark:
-                sh.conv[(p + b) % D] = (uid, p + b)
+                sh.conv[q % D] = (uid, q)
                 yield
-            sh.ring[(p + b) % D] = (uid, p + b, mark)
+            sh.ring[q % D] = (uid, q, mark)
             yield
-        sh.made = word(p + k, e)                              # after the wait for the stores
+        p += stride * k
+        sh.made[cls if stride == 2 else 0] = word(p, e)       # after the wait for the stores
         yield
-        p += k
         log["made"] += k
 
 
@@ -161,19 +177,24 @@ def mixed_lengths(r):
 
 
 def run(seed, D=16, batch=8, p_producer=0.5, n_traj=300, start=None, skip=True, lengths=mixed_lengths,
-        hold_after_claim=0, batch_start=1, p_need=0.0):
-    """hold_after_claim: the producer does not run for that many steps after each
-    claim (it sees the claim late, after the lane has formed draws itself)."""
+        hold_after_claim=0, batch_start=1, p_need=0.0, two=False):
+    """hold_after_claim: the producers do not run for that many steps after each
+    claim (they see the claim late, after the lane has formed draws itself)."""
     rng = random.Random(seed)
     sh = Shared(D)
     log = {"hits": 0, "misses": 0, "made": 0, "step": 0, "claim_step": 0, "conv_ring": 0, "conv_self": 0}
     start = start or (lambda r: r.randint(0, 50))
-    c = consumer(sh, D, rng, n_traj, start, log, lengths, p_need)
-    pr = producer(sh, D, batch, rng, log, skip, batch_start)
-    live = {"c": c, "p": pr}
+    c = consumer(sh, D, rng, n_traj, start, log, lengths, p_need, two)
+    live = {"c": c}
+    if two:
+        live["p"] = producer(sh, D, batch, rng, log, skip, batch_start, cls=0, stride=2)
+        live["p1"] = producer(sh, D, batch, rng, log, skip, batch_start, cls=1, stride=2)
+    else:
+        live["p"] = producer(sh, D, batch, rng, log, skip, batch_start)
     while "c" in live:
         held = log["step"] - log["claim_step"] < hold_after_claim
-        who = "p" if ("p" in live and not held and rng.random() < p_producer) else "c"
+        prods = [k for k in live if k != "c"]
+        who = rng.choice(prods) if (prods and not held and rng.random() < p_producer) else "c"
         log["step"] += 1
         try:
             next(live[who])
@@ -226,7 +247,7 @@ def test_the_made_reset_at_claim_is_what_prevents_stale_hits():
     # made: a made word left from 255 claims earlier then reads as a hit and
     # hands the lane another trajectory's draw
     src = open(__file__).read()
-    variant = src.replace("        sh.made = dw\n        yield\n        sh.req_id", "        sh.req_id")
+    variant = src.replace("        sh.made[0] = dw\n        sh.made[1] = dw\n        yield\n        sh.req_id", "        sh.req_id")
     assert variant != src
     ns = {"__name__": "variant"}
     exec(compile(variant, "variant", "exec"), ns)
@@ -296,6 +317,48 @@ def test_the_mark_check_is_what_keeps_stale_fields_out():
     for seed in range(6):
         try:
             ns["run"](500 + seed, D=8, batch=4, p_producer=0.2, n_traj=400, p_need=0.6,
+                      lengths=lambda r: r.choice([1, 3, r.randint(10, 80)]))
+        except AssertionError:
+            stale += 1
+    assert stale > 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("p_producer,D,batch,batch_start", [(0.5, 16, 4, 4), (0.2, 16, 4, 1), (0.85, 8, 2, 2),
+                                                            (0.5, 4, 1, 1)])
+def test_two_producers_split_by_parity(seed, p_producer, D, batch, batch_start):
+    # both producers against one lane: every hit is the lane's own draw, and
+    # both parity classes come from the ring
+    log = run(700 + seed, D=D, batch=batch, batch_start=batch_start, p_producer=p_producer, n_traj=300,
+              two=True, p_need=0.5, lengths=lambda r: r.choice([0, 1, 3, r.randint(10, 80)]))
+    assert log["hits"] > 0
+    if p_producer >= 0.5 and D >= 8:    # a ring of 4 holds two draws per producer
+        assert log["hits"] > log["misses"]
+        assert log["conv_ring"] > 0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_two_producers_epoch_reuse_and_wrap(seed):
+    for s in range(4):
+        st = {}
+        run(800 + 10 * seed + s, p_producer=0.5, n_traj=255 * 4 + 1, start=lambda r: 5, p_need=0.5, two=True,
+            batch=4, lengths=lambda r: bursts_of_finished(r, st) or r.randint(0, 2), hold_after_claim=10)
+    log = run(900 + seed, start=lambda r: (1 << 24) - r.randint(1, 40), n_traj=200, two=True, batch=4)
+    assert log["hits"] > 0
+
+
+def test_the_parity_of_the_made_word_matters():
+    # a copy of the model whose lane reads producer 0's made word for every
+    # draw takes odd draws that producer 1 has not made
+    src = open(__file__).read()
+    variant = src.replace("mw = sh.made[(dw >> 8) & 1 if two else 0]", "mw = sh.made[0]")
+    assert variant != src
+    ns = {"__name__": "variant"}
+    exec(compile(variant, "variant", "exec"), ns)
+    stale = 0
+    for seed in range(6):
+        try:
+            ns["run"](700 + seed, D=16, batch=4, p_producer=0.3, n_traj=300, two=True,
                       lengths=lambda r: r.choice([1, 3, r.randint(10, 80)]))
         except AssertionError:
             stale += 1
