@@ -513,7 +513,7 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "#endif\n"
       << "  if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, two && c == 0u ? 0x100u : 0u};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, two && c == 0u ? 0x100u : 0u, &ctl[c].made[0][lane]};\n"
       << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * ev_per_wg;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"
