@@ -509,11 +509,21 @@ std::string gen_source(const std::vector<const Model *> &models, const ModeSpec 
       << "      if (pfirst || feed0) __builtin_amdgcn_s_setprio(3);\n"
       << "      produce_item<PrecRun, Md0, SSA_RING_D, SSA_RING_NW, 2>(L, L.item[0], &ctl[0], ring, 0u, w == 1u ? 1u : 0u);\n"
       << "    }\n"
+      << "  } else if (two && w == 0u) {   // the event loop fed by both\n"
+      << "    if constexpr (SSA_RING_D >= 4) {\n"
+      << "      if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
+      << "      RingFeed<SSA_RING_D, SSA_RING_NW, true> feed{&ctl[0], ring, lane, 0u, 0u, &ctl[0].made[0][lane]};\n"
+      << "      lds_st(&ctl[0].item, 0u);\n"
+      << "      lgkm_wait();\n"
+      << "      run_item<PrecRun, Md0, " << (per_lane_rates[0] ? "true" : "false")
+      << ">(L, L.item[0], feed, blockIdx.x, gridDim.x * ev_per_wg);\n"
+      << "      lds_st(&ctl[0].item, ~0u);\n"
+      << "    }\n"
       << "  } else\n"
       << "#endif\n"
       << "  if (w < 4 && !(ded && w == 1u)) {   // PLACE_DEDICATED: wave 1 leaves SIMD 1 to wave 5\n"
       << "    if (ev_low) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(3);\n"
-      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, two && c == 0u ? 0x100u : 0u, &ctl[c].made[0][lane]};\n"
+      << "    RingFeed<SSA_RING_D, SSA_RING_NW> feed{&ctl[c], my_ring, lane, 0u, 0u, &ctl[c].made[0][lane]};\n"
       << "    const u32 slot_rank = ev_rank * gridDim.x + blockIdx.x, n_slots = gridDim.x * ev_per_wg;\n"
       << "    for (u32 i = 0; i < SSA_N_ITEMS; ++i) {\n"
       << "      lds_st(&ctl[c].item, i);\n"

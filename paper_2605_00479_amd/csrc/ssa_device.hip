@@ -800,7 +800,7 @@ struct SelfFeed {
     __device__ void request_conv(u32) const {}
 };
 
-template <int D, int NWMAX>
+template <int D, int NWMAX, bool TWO = false>
 struct RingFeed {
     static constexpr bool RING = true;
     static_assert((D & (D - 1)) == 0, "ring depth is a power of two");
@@ -809,12 +809,14 @@ struct RingFeed {
     u32 lane;
     u32 eb;         // epoch of the lane's trajectory (0: none claimed yet)
     u32 dw;         // counter word of the draw the lane takes next (event n + 1)
-    u32 cmask;      // 0x100 with two producers (a made word's byte offset is the
-                    // parity bit of the event index, bit 8 of a counter word), else 0
-    // the made word for draw dw, formed when dw changes: the load at the top of
-    // the next event then waits for no address arithmetic (a lone wave on the
-    // conversion path measured 679 cycles per event with the address formed
-    // from dw there, 648 with it formed ahead)
+    // TWO (two producers, PLACE_TWO0): the made word for draw dw, formed when dw
+    // changes (its byte offset in made is the parity bit of the event index, bit
+    // 8 of a counter word), so the load at the top of the next event waits for
+    // no address arithmetic (a lone wave on the conversion path measured 679
+    // cycles per event with the address formed from dw there, 648 with it formed
+    // ahead). With one producer the made word's address is fixed: a feed type of
+    // its own keeps that arithmetic out of every other event loop (5% of the
+    // five-network batch's step).
     const u32 *mptr;   // &ctl->made[0][lane] until the first claim
 
     // a new trajectory on this lane; the loop forms draws n and n + 1 itself.
@@ -828,7 +830,8 @@ struct RingFeed {
         lds_st(&ctl->done[lane], dw);
         lds_st(&ctl->made[0][lane], dw);
         lds_st(&ctl->made[1][lane], dw);
-        mptr = (const u32 *)((const char *)&ctl->made[0][lane] + (dw & cmask));
+        if constexpr (TWO)
+            mptr = (const u32 *)((const char *)&ctl->made[0][lane] + (dw & 0x100u));
         lds_st(&ctl->req_id[lane], id);
         lds_st(&ctl->req_lo[lane], (u32)n);
         lds_st(&ctl->req_hi[lane], (u32)(n >> 32));
@@ -869,7 +872,13 @@ struct RingFeed {
     }
 
     // the made word of the parity class of the draw the lane takes next (dw)
-    __device__ u32 made_word() const { return lds_ld(mptr); }
+    __device__ u32 made_word() const
+    {
+        if constexpr (TWO)
+            return lds_ld(mptr);
+        else
+            return lds_ld(&ctl->made[0][lane]);
+    }
 
     // slot of the draw with counter word dw: its index mod D, times the 256
     // bytes of a slot's word, is dw's index bits [8, 8 + log2 D) in place
@@ -930,7 +939,8 @@ struct RingFeed {
     __device__ void advance()
     {
         dw += 256u;
-        mptr = (const u32 *)((const char *)&ctl->made[0][lane] + (dw & cmask));
+        if constexpr (TWO)
+            mptr = (const u32 *)((const char *)&ctl->made[0][lane] + (dw & 0x100u));
     }
 };
 
