@@ -422,17 +422,29 @@ def test_full_size_telegraph_sampled(gpu, orc, mode):
     sampled_parity(gpu, orc, W, mode, [spread(W.n_traj, 120, [65_535, 65_536, 524_287])])
 
 
+# the launches the benchmark's autotuner chooses for the sweep (256 workgroups of
+# 512 threads, two windows, the first of 7 rows): MIX_F16_SR with wave 0 fed by two
+# producers (197), FP64 with wave 0 alone and fed first (29)
+BENCH_DIMER = {"MIX_F16_SR": dict(block_size=512, grid_size=256, n_chunks=2, first_window=7, placement=197),
+               "FP64": dict(block_size=512, grid_size=256, n_chunks=2, first_window=7, placement=29)}
+
+
+@pytest.mark.parametrize("launch", ["default", "bench"])
 @pytest.mark.parametrize("mode", ["FP64", "MIX_F16_SR"])
-def test_full_size_dimer_sweep_sampled(gpu, orc, mode):
+def test_full_size_dimer_sweep_sampled(gpu, orc, mode, launch):
     """Open dimer, 4,096 parameter sets x 256 trajectories in one launch,
     lengths spread over three decades: ids spread over the sets plus both ends
-    of the sets with the largest and smallest production rate."""
+    of the sets with the largest and smallest production rate; in the default
+    launch and in the one the benchmark times."""
     W = wl.config_dimer_sweep()
     it = W.items[0]
     hi, lo = int(np.argmax(it.set_rate[:, 0])), int(np.argmin(it.set_rate[:, 0]))
     tps = it.traj_per_set
     extra = [hi * tps, hi * tps + tps - 1, lo * tps, lo * tps + tps - 1]
-    sampled_parity(gpu, orc, W, mode, [spread(W.n_traj, 100, extra)])
+    kw = BENCH_DIMER[mode] if launch == "bench" else {}
+    info = sampled_parity(gpu, orc, W, mode, [spread(W.n_traj, 100, extra)], **kw)
+    if kw:
+        assert info["placement"] == kw["placement"] | 1
 
 
 @pytest.mark.parametrize("mode,launch", [("FP64", {}), ("MIX_F16_SR", dict(block_size=512, grid_size=256)),
