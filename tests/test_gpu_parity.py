@@ -184,7 +184,11 @@ def largest_network():
 
 @pytest.mark.parametrize("mode,launch", [("FP64", {}), ("MIX_F16_SR", {}), ("UNI_F16_SR", {}),
                                          ("FP64", {"block_size": 512}), ("MIX_F16_SR", {"block_size": 512}),
-                                         ("UNI_F16_SR", {"block_size": 512})])
+                                         ("UNI_F16_SR", {"block_size": 512}),
+                                         # two producers for wave 0: with a ring of 16 slots (FP64),
+                                         # and with one of 2 (mixed fp16 SR), where one producer stays
+                                         ("FP64", {"block_size": 512, "placement": 197}),
+                                         ("MIX_F16_SR", {"block_size": 512, "placement": 197})])
 def test_largest_network(gpu, orc, mode, launch):
     m = largest_network()
     assert m.n_species == 32 and m.n_reactions == 64
